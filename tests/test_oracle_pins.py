@@ -1,0 +1,352 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+The paper prints no I(q) values (its profile figures are missing and Table 1
+holds timings only), so the oracle is pinned by:
+  * closed forms of Eq. 2: one atom, two atoms at exactly known sinc values,
+    q = 0, regular polyhedra (pair multiplicities);
+  * Eq. 1 itself: the orientational average of |sum f e^{i q.r}|^2 computed by
+    Lebedev quadrature on the sphere -- an independent formula that Eq. 2 is
+    the analytic integral of;
+  * a 50-digit mpmath brute force (rounding of the FP64 sums);
+  * invariances: rotation, translation, permutation, type relabelling, the
+    bitwise power-of-two scaling r -> 2r, q -> q/2, bounds 0 < I <= (sum|f|)^2,
+    the large-q limit, per-type vs per-atom tables, atom duplication;
+  * the gradient against central finite differences of the profile and the
+    exact identities sum_i g_i = 0, sum_i x_i x g_i = 0.
+A mutation test compiles deliberately broken copies of the oracle source and
+checks that these pins reject every one of them.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+
+def sinc(x):
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(x == 0.0, 1.0, np.sin(x) / np.where(x == 0.0, 1.0, x))
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+# ---------------------------------------------------------------------------
+# Pin checks, each written against a profile function so that the mutation
+# test can run them on broken oracles too.
+# ---------------------------------------------------------------------------
+
+def pin_single_atom(profile):
+    rng = np.random.default_rng(1)
+    table = rng.uniform(0.5, 3.0, size=(3, 7))
+    q = np.linspace(0.0, 1.2, 7)
+    for t in range(3):
+        I = profile(rng.normal(size=(1, 3)), np.array([t]), table, q)
+        assert rel(I, table[t] ** 2) < 1e-15
+
+
+def pin_two_atoms(profile):
+    # r = 2 exactly; q r = pi -> sin = 0 (to 1e-16); q r = pi/2 -> sinc = 2/pi.
+    coords = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0]])
+    q = np.array([math.pi / 4, math.pi / 2, math.pi])
+    table = np.array([[1.5, 2.0, 0.5], [3.0, 0.25, 4.0]])
+    I = profile(coords, np.array([0, 1]), table, q)
+    f1, f2 = table[0], table[1]
+    expect = np.array([f1[0] ** 2 + f2[0] ** 2 + 2 * f1[0] * f2[0] * (2 / math.pi),
+                       f1[1] ** 2 + f2[1] ** 2,
+                       f1[2] ** 2 + f2[2] ** 2])
+    assert rel(I, expect) < 1e-14
+
+
+def pin_q_zero(profile):
+    m = W.random_molecule(5, 37, 4, q0=0.0, q1=0.3)
+    I = profile(m.coords, m.types, m.table, m.q)
+    f0 = m.table[m.types, 0].astype(np.float64)
+    assert rel(I[0], f0.sum() ** 2) < 1e-14
+
+
+def _tetrahedron(a):
+    v = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], dtype=np.float64)
+    return v * a / (2 * math.sqrt(2))
+
+
+def _octahedron(a):
+    v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], dtype=np.float64)
+    return v * a / math.sqrt(2)
+
+
+def _cube(a):
+    v = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)], dtype=np.float64)
+    return v * a
+
+
+def pin_polyhedra(profile):
+    a = 3.7
+    q = np.linspace(0.0, 2.5, 11)
+    f = np.exp(-0.3 * q ** 2) * 6.0
+    table = f[None, :]
+    s = lambda d: sinc(q * d)  # noqa: E731
+    cases = [
+        (_tetrahedron(a), 4 * f ** 2 * (1 + 3 * s(a))),
+        (_octahedron(a), 6 * f ** 2 * (1 + 4 * s(a) + s(math.sqrt(2) * a))),
+        (_cube(a), 8 * f ** 2 * (1 + 3 * s(a) + 3 * s(math.sqrt(2) * a) + s(math.sqrt(3) * a))),
+    ]
+    for coords, expect in cases:
+        I = profile(coords, np.zeros(len(coords), dtype=np.int32), table, q)
+        assert rel(I, expect) < 1e-13
+
+
+def eq1_quadrature(coords, types, table, q, order=131):
+    """(1/4pi) * integral over the unit sphere of |sum_j f_j(q) exp(i q n.r_j)|^2 (Eq. 1)."""
+    from scipy.integrate import lebedev_rule
+
+    x, w = lebedev_rule(order)
+    coords = np.asarray(coords, dtype=np.float64)
+    proj = coords @ x  # [N, P]: n.r_j
+    out = np.empty(len(q))
+    for m, qm in enumerate(q):
+        f = np.asarray(table, dtype=np.float64)[types, m]
+        amp = (f[:, None] * np.exp(1j * qm * proj)).sum(axis=0)
+        out[m] = float(np.sum(w * np.abs(amp) ** 2) / (4 * math.pi))
+    return out
+
+
+def pin_eq1(profile):
+    rng = np.random.default_rng(7)
+    n, t = 20, 4
+    coords = rng.uniform(-5, 5, size=(n, 3))  # D <= 17.4 A
+    types = rng.integers(0, t, size=n).astype(np.int32)
+    q = np.linspace(0.0, 3.0, 13)  # qD <= 52 << 131
+    z = np.array([1.0, 6.0, 8.0, 16.0])
+    b = np.array([0.2, 0.7, 1.1, 0.4])  # per-type widths: non-separable table
+    table = z[:, None] * np.exp(-b[:, None] * q[None, :] ** 2)
+    I = profile(coords, types, table, q)
+    assert rel(I, eq1_quadrature(coords, types, table, q)) < 1e-11
+
+
+def pin_mpmath(profile):
+    import mpmath
+
+    mpmath.mp.dps = 50
+    m = W.random_molecule(11, 12, 5, q0=0.0, q1=1.5, extent=12.0)
+    I = profile(m.coords, m.types, m.table, m.q)
+    c = [[mpmath.mpf(float(v)) for v in row] for row in m.coords]
+    exp = []
+    for k, qm in enumerate(m.q):
+        qq = mpmath.mpf(float(qm))
+        tot = mpmath.mpf(0)
+        for i in range(m.n):
+            fi = mpmath.mpf(float(m.table[m.types[i], k]))
+            for j in range(m.n):
+                fj = mpmath.mpf(float(m.table[m.types[j], k]))
+                r = mpmath.sqrt(sum((c[i][d] - c[j][d]) ** 2 for d in range(3)))
+                x = qq * r
+                tot += fi * fj * (1 if x == 0 else mpmath.sin(x) / x)
+        exp.append(float(tot))
+    assert rel(I, exp) < 1e-13
+
+
+def pin_invariances(profile):
+    m = W.random_molecule(21, 60, 9, q0=0.0, q1=1.0, extent=25.0)
+    c = m.coords.astype(np.float64)
+    base = profile(c, m.types, m.table, m.q)
+    rng = np.random.default_rng(3)
+    qmat, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    assert rel(profile(c @ qmat.T + np.array([3.0, -7.5, 11.0]), m.types, m.table, m.q), base) < 1e-12
+    perm = rng.permutation(m.n)
+    assert rel(profile(c[perm], m.types[perm], m.table, m.q), base) < 1e-13
+    relab = rng.permutation(m.table.shape[0])  # new id of old type t is relab[t]
+    table2 = np.empty_like(m.table)
+    table2[relab] = m.table
+    assert rel(profile(c, relab[m.types].astype(np.int32), table2, m.q), base) < 1e-13
+    # r -> 2r, q -> q/2 leaves every product q r bitwise unchanged.
+    assert np.array_equal(profile(2.0 * c, m.types, m.table, m.q / 2.0), base)
+    fabs = np.abs(m.table.astype(np.float64))[m.types].sum(axis=0)
+    assert np.all(base > 0) and np.all(base <= fabs ** 2 * (1 + 1e-14))
+
+
+def pin_large_q(profile):
+    m = W.random_molecule(31, 25, 3, q0=1e4, q1=2e4, extent=10.0)
+    table = np.abs(m.table.astype(np.float64)) + 1.0
+    I = profile(m.coords, m.types, table, m.q)
+    c = m.coords.astype(np.float64)
+    d = np.sqrt(((c[:, None] - c[None]) ** 2).sum(-1))
+    for k, qm in enumerate(m.q):
+        f = table[m.types, k]
+        diag = np.sum(f ** 2)
+        off = np.abs(f[:, None] * f[None]) / np.where(d == 0, np.inf, qm * d)
+        assert abs(I[k] - diag) <= off.sum() * (1 + 1e-12)
+
+
+def pin_type_factoring(profile):
+    m = W.random_molecule(41, 30, 6)
+    per_atom = m.table.astype(np.float64)[m.types]
+    I5 = profile(m.coords, m.types, m.table, m.q)
+    IN = profile(m.coords, np.arange(m.n, dtype=np.int32), per_atom, m.q)
+    assert rel(IN, I5) < 1e-14
+
+
+def pin_duplication(profile):
+    m = W.random_molecule(51, 15, 6, t=2)
+    c = m.coords.astype(np.float64)
+    table = m.table.astype(np.float64)
+    c2 = np.vstack([c, c[:1]])
+    t2 = np.concatenate([m.types, m.types[:1]]).astype(np.int32)
+    table3 = np.vstack([table, 2.0 * table[m.types[0]][None]])
+    t3 = m.types.copy()
+    t3[0] = table.shape[0]
+    assert rel(profile(c2, t2, table, m.q), profile(c, t3, table3, m.q)) < 1e-13
+
+
+PINS = [pin_single_atom, pin_two_atoms, pin_q_zero, pin_polyhedra, pin_eq1, pin_mpmath, pin_invariances,
+        pin_large_q, pin_type_factoring, pin_duplication]
+
+
+@pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
+def test_oracle_profile_pin(pin):
+    pin(oracle.profile)
+
+
+def test_numpy_transcription_matches_c_oracle():
+    m = W.random_molecule(61, 45, 8)
+    assert rel(oracle.profile_numpy(m.coords, m.types, m.table, m.q),
+               oracle.profile(m.coords, m.types, m.table, m.q)) < 1e-14
+
+
+def test_oracle_thread_count_independent():
+    m = W.random_molecule(71, 300, 6)
+    a = oracle.profile(m.coords, m.types, m.table, m.q, threads=1)
+    b = oracle.profile(m.coords, m.types, m.table, m.q, threads=3)
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# Gradient pins
+# ---------------------------------------------------------------------------
+
+def _grad_case():
+    m = W.random_molecule(81, 18, 7, q0=0.0, q1=1.2, extent=9.0)
+    rng = np.random.default_rng(5)
+    w = rng.normal(size=len(m.q))
+    return m.coords.astype(np.float64), m.types, m.table.astype(np.float64), m.q, w
+
+
+def test_grad_vs_central_differences():
+    c, t, tab, q, w = _grad_case()
+    g = oracle.grad(c, t, tab, q, w)
+    h = 1e-5
+    num = np.zeros_like(c)
+    for i in range(c.shape[0]):
+        for d in range(3):
+            cp = c.copy()
+            cm = c.copy()
+            cp[i, d] += h
+            cm[i, d] -= h
+            num[i, d] = (w @ oracle.profile(cp, t, tab, q) - w @ oracle.profile(cm, t, tab, q)) / (2 * h)
+    assert np.linalg.norm(g - num) / np.linalg.norm(num) < 1e-7
+
+
+def test_grad_identities():
+    c, t, tab, q, w = _grad_case()
+    g = oracle.grad(c, t, tab, q, w)
+    scale = np.abs(g).sum()
+    assert np.abs(g.sum(axis=0)).max() < 1e-12 * scale
+    torque = np.cross(c, g).sum(axis=0)
+    assert np.abs(torque).max() < 1e-12 * scale * np.abs(c).max()
+
+
+def test_grad_atom_subset_matches_full():
+    c, t, tab, q, w = _grad_case()
+    g = oracle.grad(c, t, tab, q, w)
+    sub = np.array([3, 0, 17, 9])
+    assert np.array_equal(oracle.grad(c, t, tab, q, w, atoms=sub), g[sub])
+
+
+def test_grad_q_zero_and_coincident_atoms_are_zero():
+    c = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 2.0, 0.5]])
+    tab = np.array([[2.0, 1.0]])
+    q = np.array([0.0, 0.7])
+    g = oracle.grad(c, np.zeros(3, dtype=np.int32), tab, q, np.array([1.0, 0.0]))
+    assert np.all(g == 0.0)
+
+
+def test_chi2_weights_are_the_derivative():
+    rng = np.random.default_rng(9)
+    T = rng.uniform(1, 2, size=6)
+    I = T * (1 + 0.03 * rng.normal(size=6))
+    val, w = oracle.chi2(I, T)
+    h = 1e-6
+    for k in range(6):
+        e = np.zeros(6)
+        e[k] = h
+        num = (oracle.chi2(I + e, T)[0] - oracle.chi2(I - e, T)[0]) / (2 * h)
+        assert abs(num - w[k]) <= 1e-6 * abs(w).max()
+
+
+# ---------------------------------------------------------------------------
+# Mutation test: plausible mistakes planted in copies of the oracle's C source
+# (on the CPU) must each be caught by at least one pin.
+# ---------------------------------------------------------------------------
+
+MUTANTS = {
+    "no_doubling": ("double term = 2.0 * fk[m]", "double term = 1.0 * fk[m]"),
+    "no_diagonal": ("neu_add(&tot, f * f);", "(void)0;"),
+    "sinc0_is_zero": ("return x == 0.0 ? 1.0 : sin(x) / x;", "return x == 0.0 ? 0.0 : sin(x) / x;"),
+    "wrong_partner_type": ("const double* fj = table + (int64_t)types[j] * nq;\n        for (int32_t m = 0; m < nq; ++m) {\n          double term",
+                           "const double* fj = table + (int64_t)types[k] * nq;\n        for (int32_t m = 0; m < nq; ++m) {\n          double term"),
+    "q_off_by_one": ("sinc(q[m] * r)", "sinc(q[m > 0 ? m - 1 : 0] * r)"),
+    "dropped_dz": ("sqrt(dx * dx + dy * dy + dz * dz);\n        const double* fj",
+                   "sqrt(dx * dx + dy * dy);\n        const double* fj"),
+    "transposed_table": ("double f = table[(int64_t)types[k] * nq + m];", "double f = table[(int64_t)m * t + types[k] % t];"),
+}
+
+
+def _build_mutant(tmp_path, name, old, new):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "debye_oracle.c")).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new, 1))
+    so = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", str(path), "-o", str(so), "-lm"])
+    lib = ctypes.CDLL(str(so))
+    P = ctypes.c_void_p
+    lib.oracle_debye_profile.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.c_int]
+
+    def profile(coords, types, table, q):
+        c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(-1, 3))
+        t = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
+        tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+        qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+        out = np.zeros(len(qq))
+        a = np.zeros(len(qq))
+        lib.oracle_debye_profile(c.ctypes.data, t.ctypes.data, c.shape[0], tab.ctypes.data, tab.shape[0],
+                                 qq.ctypes.data, len(qq), out.ctypes.data, a.ctypes.data, 1)
+        return out
+
+    return profile
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_reject_mutant(tmp_path, name):
+    old, new = MUTANTS[name]
+    profile = _build_mutant(tmp_path, name, old, new)
+    caught = []
+    for pin in PINS:
+        if pin is pin_mpmath:
+            continue  # slow, and redundant for structural mistakes
+        try:
+            pin(profile)
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"no pin caught mutant {name}"
