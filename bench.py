@@ -1,0 +1,231 @@
+"""Benchmark of the Debye-summation hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
+
+A step is one full profile evaluation (pack -> pair kernel -> FP64 reduce)
+of the 50,000-atom double-helix rod on a 200-point q grid over [0, 1] 1/A,
+with inputs already resident in HBM.  The headline value is the whole-job
+pair.q rate: N(N-1)/2 pairs times the 199 q values with q > 0, per second.
+
+The JSON line also carries
+  roofline      the pair kernel's algorithmic FP32 rate (10 flops per pair.q)
+                from HIP events recorded on its own launch stream, against the
+                MI355X FP32 vector peak (157.3 TFLOP/s);
+  cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
+                (the same molecule, a subset of q values);
+  accuracy      max relative error per q against the stored oracle profile;
+  batched/grad  the batched and gradient forms against plain launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, 256 CU x 2.4 GHz x 256 flop/clk
+FLOPS_PER_PAIR_Q = 10.0   # forward: 4 FMA rotation + 1 FMA accumulate (the metric's convention)
+FLOPS_PER_PAIR_Q_ADJ = 12.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pair_q(n: int, q: np.ndarray) -> float:
+    return n * (n - 1) / 2.0 * float(np.count_nonzero(q > 0))
+
+
+def cpu_baseline(m, budget_q=(50, 100, 150, 199)):
+    import oracle
+
+    pick = np.array(budget_q)
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
+    dt = time.perf_counter() - t0
+    work = m.n * (m.n - 1) / 2.0 * len(pick)
+    return {"value": work / dt, "unit": "pair*q/s", "cores": threads, "kind": "oracle",
+            "sample": f"dna_rod_50k, all {m.n} atoms, {len(pick)} of the 200 q values "
+                      f"(indices {list(budget_q)}), FP64, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1306_2258_amd as sd
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    m = W.dna_rod_50k()
+    coords = torch.from_numpy(m.coords).to(dev)
+    types = torch.from_numpy(m.types).to(dev)
+    table = torch.from_numpy(m.table).to(dev)
+    ctx = sd.Context(0)
+    out = torch.empty(len(m.q), dtype=torch.float64, device=dev)
+    log(f"workload dna_rod_50k N={m.n} Nq={len(m.q)}")
+
+    for _ in range(args.warmup):
+        sd.debye_profile(coords, types, table, m.q, ctx=ctx, out=out)
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.enable_timing(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sd.debye_profile(coords, types, table, m.q, ctx=ctx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ctx.enable_timing(False)
+    kt = ctx.read_timing()
+    ms_step = ms_total / args.steps
+    work = pair_q(m.n, m.q)
+    value = work / (ms_step / 1e3)
+    kern_ms = kt["forward_ms"] / max(kt["forward_launches"], 1)
+    achieved = FLOPS_PER_PAIR_Q * work / (kern_ms / 1e3) / 1e12
+    bj, qc = ctx.variant()
+    log(f"{ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), pair kernel {kern_ms:.3f} ms, "
+        f"{value:.4e} pair*q/s, variant bj={bj} qc={qc}")
+
+    result = {
+        "metric": "pair*q sinc evaluations per second (Debye sum, N=50,000 rod, Nq=200)",
+        "value": value,
+        "unit": "pair*q/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dna_rod_50k", "atoms": m.n, "nq": len(m.q), "q_range": [0.0, 1.0], "types": 5,
+                   "pair_q_per_step": work, "variant": {"bj": bj, "qc": qc}},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_forward", "kernel_ms": kern_ms, "flops_per_pair_q": FLOPS_PER_PAIR_Q},
+    }
+
+    # accuracy of the timed output against the stored FP64 oracle profile
+    gold = os.path.join(ROOT, "tests", "golden", "dna_rod_50k.txt")
+    if os.path.exists(gold):
+        ref = np.loadtxt(gold)
+        got = out.cpu().numpy()
+        err = np.abs(got - ref[:, 1]) / ref[:, 1]
+        result["accuracy"] = {"max_rel_err": float(err.max()), "argmax_q": float(ref[err.argmax(), 0]),
+                              "median_rel_err": float(np.median(err)),
+                              "kappa_at_max": float(ref[err.argmax(), 2] / ref[err.argmax(), 1])}
+        log(f"max rel err vs oracle {err.max():.3e}")
+
+    if not args.no_extras:
+        try:
+            result["batched"] = bench_batched(sd, W, torch, dev)
+        except Exception as exc:  # reported, never hides the headline
+            result["batched"] = {"error": str(exc)[:200]}
+        try:
+            result["grad"] = bench_grad(sd, W, torch, dev)
+        except Exception as exc:
+            result["grad"] = {"error": str(exc)[:200]}
+
+    if not args.no_cpu:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(m)
+        log(f"cpu oracle {result['cpu_baseline']['value']:.3e} pair*q/s on {result['cpu_baseline']['cores']} threads")
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def _time(fn, torch, reps=3):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(sd, W, torch, dev):
+    """256 globular structures (500..8000 atoms) on a 100-point grid: one
+    batched evaluation (plan replay) against 256 plain calls."""
+    log("batched: generating the 256-structure ensemble")
+    e = W.globular_ensemble()
+    coords = torch.from_numpy(e.coords).to(dev)
+    types = torch.from_numpy(e.types).to(dev)
+    table = torch.from_numpy(e.table).to(dev)
+    work = sum(pair_q(int(n), e.q) for n in e.sizes)
+    ctx = sd.Context(0)
+    ms_batched = _time(lambda: sd.debye_profile_batched(coords, types, e.offsets, table, e.q, ctx=ctx), torch)
+    res = {"structures": int(len(e.sizes)), "atoms": int(e.offsets[-1]), "nq": len(e.q), "pair_q": work,
+           "ms_batched_call": ms_batched}
+    try:
+        plan = sd.BatchedPlan(coords, types, e.offsets, table, e.q, ctx=ctx)
+        res["ms_plan_replay"] = _time(plan.execute, torch)
+        plan.close()
+    except sd.SasError as exc:
+        res["plan"] = str(exc)[:120]
+    views = [(coords[int(a):int(b)], types[int(a):int(b)]) for a, b in zip(e.offsets[:-1], e.offsets[1:])]
+    ctx2 = sd.Context(0)
+
+    def plain():
+        for c, t in views:
+            sd.debye_profile(c, t, table, e.q, ctx=ctx2)
+
+    res["ms_plain_launches"] = _time(plain, torch, reps=2)
+    best = min(res.get("ms_plan_replay", ms_batched), ms_batched)
+    res["speedup_vs_plain"] = res["ms_plain_launches"] / best
+    res["pair_q_per_s"] = work / (best / 1e3)
+    log(f"batched {best:.3f} ms vs plain {res['ms_plain_launches']:.3f} ms")
+    return res
+
+
+def bench_grad(sd, W, torch, dev):
+    """20,000-atom lattice, 100 q: forward + adjoint (chi^2 weights) against
+    the forward alone."""
+    m = W.lattice_20k()
+    coords = torch.from_numpy(m.coords).to(dev)
+    types = torch.from_numpy(m.types).to(dev)
+    table = torch.from_numpy(m.table).to(dev)
+    ctx = sd.Context(0)
+    fwd = sd.debye_profile(coords, types, table, m.q, ctx=ctx)
+    target = fwd * 1.01
+    w = 2.0 * (fwd - target) / (0.01 * target) ** 2
+    ms_fwd = _time(lambda: sd.debye_profile(coords, types, table, m.q, ctx=ctx), torch)
+    ms_grad = _time(lambda: sd.debye_grad(coords, types, table, m.q, w, with_profile=True, ctx=ctx), torch)
+    work = pair_q(m.n, m.q)
+    log(f"grad {ms_grad:.3f} ms vs forward {ms_fwd:.3f} ms")
+    return {"atoms": m.n, "nq": len(m.q), "ms_forward": ms_fwd, "ms_forward_plus_adjoint": ms_grad,
+            "ratio": ms_grad / ms_fwd, "fd_equivalent_speedup": 6 * m.n * ms_fwd / ms_grad,
+            "adjoint_tflops_alg": FLOPS_PER_PAIR_Q_ADJ * work / (ms_grad / 1e3) / 1e12}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

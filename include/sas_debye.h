@@ -1,0 +1,187 @@
+/*
+ * sas_debye.h -- C ABI of the MI355X (gfx950) Debye-summation library.
+ *
+ * The library evaluates the small-angle-scattering profile of a molecule by
+ * direct summation over all atom pairs (Berlin, Gumerov, Duraiswami, Fushman,
+ * "Performance of a GPU-based Direct Summation Algorithm for Computation of
+ * Small Angle Scattering Profile", Background section, Eq. 2):
+ *
+ *     I(q) = sum_k sum_j f_k(q) f_j(q) sin(q r_jk) / (q r_jk),   sin(0)/0 := 1
+ *
+ * Form factors are given per atom *type*: f_k(q_m) = table[type_k * Nq + m].
+ * One type per atom reproduces the paper's per-atom form factors (the text
+ * below Eq. 2); a handful of element types is the common case.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Units: coordinates in Angstrom, q in 1/Angstrom, no 2pi or 4pi factors.
+ *  - "dev" pointers are HIP device pointers on the context's device; "host"
+ *    pointers are ordinary host memory and are only read before the call
+ *    returns.  The caller owns every buffer; the library never frees caller
+ *    memory.  It owns only sas_ctx and sas_plan objects.
+ *  - Device work is enqueued asynchronously on `stream` (a hipStream_t passed
+ *    as void*; NULL is the default stream).  Results are valid once the
+ *    stream reaches the call.  No call synchronises the stream.
+ *  - Scratch memory is the caller's `workspace` (dev, 256-byte aligned) of at
+ *    least the size the matching *_workspace_size query returns.
+ *  - The q grid must be uniform: q_m = q_0 + m dq within 8 ulp of max q,
+ *    q_0 >= 0, strictly increasing, all finite (Results section: profiles on
+ *    uniformly spaced q).  Nq = 1 is always accepted.
+ *  - Results are FP64.  Pair terms are evaluated in FP32 from FP64 per-pair
+ *    set-up values; every cross-lane and cross-block sum beyond one 64-lane
+ *    wave is FP64 and in a fixed order, so two identical calls give bitwise
+ *    identical results.
+ *  - Errors: a status code, plus a thread-local message from
+ *    sas_last_error().  Host-detectable argument errors are reported before
+ *    any device work is enqueued and leave the outputs untouched.  Device-side
+ *    content errors (a type id outside [0,T), non-finite coordinates) are not
+ *    checked: they give unspecified values, never an out-of-bounds access,
+ *    because type ids are clamped when the table is read.
+ *  - Thread safety: calls on distinct contexts, plans and workspaces may run
+ *    concurrently.  Calls that share a workspace or plan must be ordered on
+ *    one stream.
+ */
+#ifndef SAS_DEBYE_H
+#define SAS_DEBYE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SAS_OK = 0,
+  SAS_ERR_INVALID_ARG = 1,         /* null pointer, negative size, bad offsets, ...       */
+  SAS_ERR_Q_NOT_UNIFORM = 2,       /* q is not finite / non-negative / increasing / uniform */
+  SAS_ERR_UNSUPPORTED = 3,         /* a size beyond the documented limits                  */
+  SAS_ERR_WORKSPACE_TOO_SMALL = 4, /* ws_bytes below the size the query returns            */
+  SAS_ERR_OUT_OF_MEMORY = 5,       /* a host or device allocation of the library failed   */
+  SAS_ERR_HIP = 6                  /* a HIP runtime call failed; see sas_last_error()      */
+} sas_status;
+
+/* Limits of this version. */
+#define SAS_MAX_TYPES 4096          /* T                                           */
+#define SAS_MAX_NQ 65536            /* Nq                                          */
+#define SAS_MAX_ATOMS 100000000LL   /* atoms per structure                         */
+
+typedef struct sas_ctx sas_ctx;   /* device binding, tuning choices, staging buffers */
+typedef struct sas_plan sas_plan; /* batched schedule bound to buffers + captured graph */
+
+/* Library version as an integer MAJOR*10000 + MINOR*100 + PATCH. */
+int sas_version(void);
+
+/* Create a context on HIP device `device` (must be a gfx950 GPU).  *out is
+ * set on success.  Errors: SAS_ERR_INVALID_ARG (out NULL, no such device,
+ * not gfx950), SAS_ERR_HIP, SAS_ERR_OUT_OF_MEMORY. */
+sas_status sas_create(int device, sas_ctx** out);
+void sas_destroy(sas_ctx* ctx); /* NULL is ignored; waits for nothing */
+
+/* Thread-local, human-readable detail of the last failed call on this thread. */
+const char* sas_last_error(void);
+const char* sas_status_string(sas_status s);
+
+/* Host-only q-grid analysis (no device work, no context needed).
+ * q: host [nq].  On SAS_OK writes q0 = q[0] and dq = (q[nq-1]-q[0])/(nq-1)
+ * (dq = 0 when nq == 1).  Errors: SAS_ERR_INVALID_ARG (q NULL, nq <= 0 or
+ * > SAS_MAX_NQ), SAS_ERR_Q_NOT_UNIFORM. */
+sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq);
+
+/* Workspace bytes needed by sas_debye_profile (grad = 0) or sas_debye_grad
+ * (grad = 1) for these sizes.  Returns 0 for invalid sizes. */
+size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad);
+
+/*
+ * Plain Debye profile (Eq. 2).
+ *   coords  dev  float [n][3]     atom positions, Angstrom (AoS x,y,z)
+ *   types   dev  int32 [n]        type id of each atom, in [0, t)
+ *   n                             number of atoms, 0 <= n <= SAS_MAX_ATOMS
+ *   table   dev  float [t][nq]    f_type(q_m), row-major
+ *   t                             number of types, 1 <= t <= SAS_MAX_TYPES
+ *   q       host double [nq]      uniform grid (see conventions)
+ *   nq                            1 <= nq <= SAS_MAX_NQ
+ *   I_out   dev  double [nq]      written: I(q_m)
+ *   workspace/ws_bytes            dev scratch, >= sas_debye_workspace_size(ctx,n,t,nq,0)
+ *   stream                        hipStream_t as void*
+ * n = 0 gives I = 0; n = 1 gives f(q)^2; q_m = 0 gives (sum_k f_k(0))^2.
+ * Coincident distinct atoms contribute f_k f_j (the sinc limit).
+ */
+sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                             const float* table, int32_t t, const double* q, int32_t nq, double* I_out,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Batched profiles of S structures that share one table and one q grid (the
+ * ensemble use the paper's introduction motivates: many conformations or
+ * structures evaluated together).  Atoms of structure s are rows
+ * [offsets[s], offsets[s+1]) of coords/types; offsets is a HOST int64 [S+1]
+ * array with offsets[0] = 0, non-decreasing.  I_out is dev double [S][nq].
+ * All structures run in one launch sequence; large structures are scheduled
+ * first.  Same limits and edge cases as the plain call, per structure.
+ */
+size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offsets, int32_t S, int32_t t,
+                                        int32_t nq);
+sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const int32_t* types,
+                                     const int64_t* offsets, int32_t S, const float* table, int32_t t,
+                                     const double* q, int32_t nq, double* I_out, void* workspace, size_t ws_bytes,
+                                     void* stream);
+
+/*
+ * Batched plan: binds the device buffers above once, chooses the tile shape by
+ * timing candidate variants on first execution (the choice is cached in the
+ * context per workload shape), captures the launch sequence in a hipGraph and
+ * replays it on each execute.  The caller may rewrite coords/types/table in
+ * place between executes; sizes, offsets and q are fixed at creation.
+ * The plan must be destroyed before the context.
+ */
+sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int32_t* types,
+                                   const int64_t* offsets, int32_t S, const float* table, int32_t t,
+                                   const double* q, int32_t nq, double* I_out, void* workspace, size_t ws_bytes,
+                                   sas_plan** out);
+sas_status sas_plan_execute(sas_plan* plan, void* stream);
+void sas_plan_destroy(sas_plan* plan);
+
+/*
+ * Vector-Jacobian product of the profile w.r.t. the coordinates:
+ *     grad_out[i][k] = sum_m dL_dI[m] * dI(q_m)/dx_ik
+ *                    = sum_{j != i} 2 sum_m dL_dI[m] f_i f_j
+ *                        (cos(q_m r)/r - sin(q_m r)/(q_m r^2)) (x_ik - x_jk)/r
+ * (the derivative of Eq. 2; terms with q_m = 0 or r = 0 vanish).
+ *   dL_dI    dev double [nq]    weights (e.g. dchi2/dI)
+ *   grad_out dev double [n][3]  written, in the caller's atom order
+ *   I_out    dev double [nq] or NULL: if given, the profile is written too
+ * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 1).
+ */
+sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
+                          int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
+                          double* I_out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Tuning controls (optional).  sas_set_variant forces the forward tile shape
+ * for subsequent calls on ctx: bj = atoms per J block (64, 128, 256 or 512;
+ * 0 = automatic) and qc = q values per chunk (one of 16, 32, 64, 100, 128,
+ * 200; 0 = automatic).  Returns SAS_ERR_INVALID_ARG for other values.
+ * sas_get_variant reports the shape the last forward call used.
+ */
+sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc);
+sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
+
+/*
+ * Kernel timing (optional, for benchmarks).  While enabled, every forward and
+ * adjoint pair-kernel launch on ctx is bracketed by two HIP events recorded on
+ * the launch stream.  sas_read_timing waits for those events, writes the
+ * summed device time of the forward (pair) kernels in ms and their launch
+ * count (and the same for the adjoint kernels; either pointer may be NULL),
+ * then clears the record.  Disabled by default; enabling costs two event
+ * records per launch.
+ */
+sas_status sas_enable_timing(sas_ctx* ctx, int on);
+sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_launches, double* adjoint_ms,
+                           int64_t* adjoint_launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAS_DEBYE_H */

@@ -1,0 +1,551 @@
+// C ABI of the Debye-summation library: argument checks, q-grid analysis,
+// schedule and workspace layout, launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sas_debye.h"
+#include "sas_kernels.hpp"
+
+using sas::DescView;
+using sas::Geometry;
+using sas::StructDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+sas_status fail(sas_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define SAS_HIP(call)                                                                           \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess) return fail(SAS_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+const int32_t kQcTemplates[] = {16, 32, 50, 64, 100, 128, 150, 200};
+
+}  // namespace
+
+struct sas_ctx {
+  int device = 0;
+  int cu_count = 0;
+  int32_t force_bj = 0, force_qc = 0;
+  int32_t last_bj = 0, last_qc = 0;
+  // pinned staging for the batched call's descriptor upload
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t pinned_ev = nullptr;
+  bool pinned_used = false;
+  std::mutex mu;
+  // tuned (bj) per workload key, filled by plans
+  std::map<std::string, int32_t> tuned_bj;
+  // optional kernel timing: event pairs around pair-kernel launches
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+hipEvent_t take_event(sas_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around one kernel launch when timing is on.
+struct LaunchTimer {
+  sas_ctx* ctx;
+  hipStream_t st;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* rec;
+  hipEvent_t a = nullptr, b = nullptr;
+  LaunchTimer(sas_ctx* c, hipStream_t s, bool adjoint) : ctx(c), st(s), rec(nullptr) {
+    if (!c || !c->timing) return;
+    rec = adjoint ? &c->ev_adj : &c->ev_fwd;
+    a = take_event(c);
+    b = take_event(c);
+    if (a && b) (void)hipEventRecord(a, st);
+  }
+  ~LaunchTimer() {
+    if (!rec || !a || !b) return;
+    (void)hipEventRecord(b, st);
+    rec->emplace_back(a, b);
+  }
+};
+
+// RAII: make ctx's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct Schedule {
+  Geometry geo{};
+  int32_t qc = 0, qc_template = 0;
+  int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
+  int32_t S = 0;
+  int64_t n_total = 0;
+  int64_t n_pack = 0, n_strips = 0, n_slices = 0;
+  std::vector<StructDesc> desc;  // execution order
+};
+
+struct Layout {
+  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, desc = 0, tabp = 0, partial = 0, slices = 0, total = 0;
+};
+
+int32_t pick_qc_template(int32_t qc) {
+  for (int32_t t : kQcTemplates)
+    if (t >= qc) return t;
+  return 200;
+}
+
+int32_t default_bj(int64_t max_n) {
+  if (max_n >= 2048) return 256;
+  if (max_n >= 512) return 128;
+  return 64;
+}
+
+// Build the schedule for structure sizes `sizes` (caller order).
+Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
+                       int32_t bj_override = 0) {
+  Schedule sc;
+  sc.S = static_cast<int32_t>(sizes.size());
+  int64_t max_n = 0;
+  for (int64_t n : sizes) {
+    max_n = std::max(max_n, n);
+    sc.n_total += n;
+  }
+  // q chunking: one chunk up to 200 values, else balanced chunks of <= 200
+  int32_t qc = Nq;
+  if (ctx && ctx->force_qc > 0) {
+    qc = std::min(ctx->force_qc, Nq);
+    sc.qc_template = ctx->force_qc;
+  } else {
+    const int32_t nch = (Nq + 199) / 200;
+    qc = (Nq + nch - 1) / nch;
+    sc.qc_template = pick_qc_template(qc);
+  }
+  sc.qc = qc;
+  sc.nchunks = (Nq + qc - 1) / qc;
+  sc.ldt = (sc.nchunks - 1) * qc + sc.qc_template;
+  int32_t bj = bj_override > 0 ? bj_override : (ctx && ctx->force_bj > 0 ? ctx->force_bj : default_bj(max_n));
+  sc.geo.bj = bj;
+  sc.geo.c = bj / sas::kWave;
+  // strips of g J blocks: g = 1 unless the partial rows would exceed 256 MiB
+  for (int32_t g = 1;; g *= 2) {
+    sc.geo.g = g;
+    int64_t strips = 0;
+    for (int64_t n : sizes) strips += sas::strips_of(n, sc.geo);
+    if (static_cast<double>(strips) * Nq * 8.0 <= 256.0 * 1024 * 1024 || g >= 1024) break;
+  }
+  // execution order: largest structure first (longest-processing-time order)
+  std::vector<int32_t> order(sc.S);
+  for (int32_t s = 0; s < sc.S; ++s) order[s] = s;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return sizes[a] > sizes[b]; });
+  // atom offsets in caller order
+  std::vector<int64_t> off(sc.S + 1, 0);
+  for (int32_t s = 0; s < sc.S; ++s) off[s + 1] = off[s] + sizes[s];
+  sc.desc.resize(sc.S);
+  int64_t strip = 0, slice = 0, pack = 0;
+  for (int32_t k = 0; k < sc.S; ++k) {
+    const int32_t s = order[k];
+    StructDesc& d = sc.desc[k];
+    std::memset(&d, 0, sizeof(d));
+    d.atom_off = off[s];
+    d.n = static_cast<int32_t>(sizes[s]);
+    d.orig = s;
+    d.strip_off = strip;
+    d.n_strips = static_cast<int32_t>(sas::strips_of(sizes[s], sc.geo));
+    d.slice_off = slice;
+    d.n_slices = static_cast<int32_t>(sas::slices_of(d.n_strips));
+    d.pack_off = static_cast<int32_t>(pack);
+    strip += d.n_strips;
+    slice += d.n_slices;
+    pack += (sizes[s] + sas::kPackBlock - 1) / sas::kPackBlock;
+  }
+  sc.n_strips = strip;
+  sc.n_slices = slice;
+  sc.n_pack = pack;
+  return sc;
+}
+
+Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
+  Layout L;
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = p;
+    p = align_up(p + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.xyz = take(sizeof(double4) * sc.n_total);
+  L.tsort = take(sizeof(int32_t) * sc.n_total);
+  L.perm = take(sizeof(int32_t) * sc.n_total);
+  L.bcount = take(sizeof(int32_t) * sc.n_pack * T);
+  L.toff = take(sizeof(int32_t) * static_cast<size_t>(sc.S) * (T + 1));
+  L.desc = take(sc.S > 1 ? sizeof(StructDesc) * sc.S : 0);
+  L.tabp = take(sizeof(float) * static_cast<size_t>(T) * sc.ldt);
+  L.partial = take(sizeof(double) * sc.n_strips * Nq);
+  L.slices = take(sizeof(double) * sc.n_slices * Nq);
+  L.total = p;
+  return L;
+}
+
+sas_status check_sizes(int64_t n, int32_t T, int32_t Nq) {
+  if (n < 0 || n > SAS_MAX_ATOMS) return fail(n < 0 ? SAS_ERR_INVALID_ARG : SAS_ERR_UNSUPPORTED, "atom count %lld outside [0, %lld]", (long long)n, (long long)SAS_MAX_ATOMS);
+  if (T <= 0) return fail(SAS_ERR_INVALID_ARG, "type count %d must be >= 1", T);
+  if (T > SAS_MAX_TYPES) return fail(SAS_ERR_UNSUPPORTED, "type count %d above %d", T, SAS_MAX_TYPES);
+  if (Nq <= 0) return fail(SAS_ERR_INVALID_ARG, "q count %d must be >= 1", Nq);
+  if (Nq > SAS_MAX_NQ) return fail(SAS_ERR_UNSUPPORTED, "q count %d above %d", Nq, SAS_MAX_NQ);
+  return SAS_OK;
+}
+
+sas_status check_offsets(const int64_t* offsets, int32_t S, std::vector<int64_t>* sizes) {
+  if (S < 0) return fail(SAS_ERR_INVALID_ARG, "S = %d must be >= 0", S);
+  if (!offsets) return fail(SAS_ERR_INVALID_ARG, "offsets is NULL");
+  if (offsets[0] != 0) return fail(SAS_ERR_INVALID_ARG, "offsets[0] = %lld, must be 0", (long long)offsets[0]);
+  sizes->resize(S);
+  for (int32_t s = 0; s < S; ++s) {
+    const int64_t n = offsets[s + 1] - offsets[s];
+    if (n < 0) return fail(SAS_ERR_INVALID_ARG, "offsets decrease at %d", s);
+    if (n > SAS_MAX_ATOMS) return fail(SAS_ERR_UNSUPPORTED, "structure %d has %lld atoms", s, (long long)n);
+    (*sizes)[s] = n;
+  }
+  if (offsets[S] > (int64_t)INT32_MAX) return fail(SAS_ERR_UNSUPPORTED, "more than 2^31-1 atoms in total");
+  return SAS_OK;
+}
+
+DescView view_of(const Schedule& sc, const void* ws, const Layout& L) {
+  DescView v;
+  std::memset(&v, 0, sizeof(v));
+  v.S = sc.S;
+  if (sc.S == 1) v.one = sc.desc[0];
+  v.arr = sc.S > 1 ? reinterpret_cast<const StructDesc*>(static_cast<const char*>(ws) + L.desc) : nullptr;
+  return v;
+}
+
+// Enqueue pack -> forward -> reduce for a prepared schedule.  Descriptors must
+// already be in the workspace when S > 1.
+sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, const float* coords,
+                           const int32_t* types, const float* table, int32_t T, int32_t Nq, double q0, double dq,
+                           double* I_out, void* ws, hipStream_t st) {
+  char* w = static_cast<char*>(ws);
+  DescView sd = view_of(sc, ws, L);
+  auto* xyz = reinterpret_cast<double4*>(w + L.xyz);
+  auto* tsort = reinterpret_cast<int32_t*>(w + L.tsort);
+  auto* perm = reinterpret_cast<int32_t*>(w + L.perm);
+  auto* bcount = reinterpret_cast<int32_t*>(w + L.bcount);
+  auto* toff = reinterpret_cast<int32_t*>(w + L.toff);
+  auto* partial = reinterpret_cast<double*>(w + L.partial);
+  auto* slices = reinterpret_cast<double*>(w + L.slices);
+  auto* tabp = reinterpret_cast<float*>(w + L.tabp);
+  SAS_HIP(sas::launch_pad_table(table, T, Nq, sc.ldt, tabp, st));
+  SAS_HIP(sas::launch_pack(coords, types, sd, sc.S, sc.n_pack, T, bcount, toff, xyz, tsort, perm, st));
+  sas::ForwardArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sd = sd;
+  a.geo = sc.geo;
+  a.xyz = xyz;
+  a.tsort = tsort;
+  a.toff = toff;
+  a.tabp = tabp;
+  a.ldt = sc.ldt;
+  a.partial = partial;
+  a.T = T;
+  a.Nq = Nq;
+  a.qc = sc.qc;
+  a.q0 = q0;
+  a.dq = dq;
+  {
+    LaunchTimer timer(ctx, st, false);
+    SAS_HIP(sas::launch_forward(a, sc.n_strips, sc.qc_template, st));
+  }
+  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, toff, table, T, Nq, q0, dq, I_out, st));
+  return SAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sas_version(void) { return 100; }
+
+const char* sas_last_error(void) { return g_err.c_str(); }
+
+const char* sas_status_string(sas_status s) {
+  switch (s) {
+    case SAS_OK: return "SAS_OK";
+    case SAS_ERR_INVALID_ARG: return "SAS_ERR_INVALID_ARG";
+    case SAS_ERR_Q_NOT_UNIFORM: return "SAS_ERR_Q_NOT_UNIFORM";
+    case SAS_ERR_UNSUPPORTED: return "SAS_ERR_UNSUPPORTED";
+    case SAS_ERR_WORKSPACE_TOO_SMALL: return "SAS_ERR_WORKSPACE_TOO_SMALL";
+    case SAS_ERR_OUT_OF_MEMORY: return "SAS_ERR_OUT_OF_MEMORY";
+    case SAS_ERR_HIP: return "SAS_ERR_HIP";
+  }
+  return "unknown status";
+}
+
+sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq) {
+  if (!q) return fail(SAS_ERR_INVALID_ARG, "q is NULL");
+  if (nq <= 0 || nq > SAS_MAX_NQ) return fail(SAS_ERR_INVALID_ARG, "q count %d outside [1, %d]", nq, SAS_MAX_NQ);
+  for (int32_t m = 0; m < nq; ++m) {
+    if (!std::isfinite(q[m])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] is not finite", m);
+    if (q[m] < 0.0) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] = %g is negative", m, q[m]);
+    if (m > 0 && !(q[m] > q[m - 1])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q is not strictly increasing at %d", m);
+  }
+  const double a = q[0];
+  const double d = nq > 1 ? (q[nq - 1] - q[0]) / (nq - 1) : 0.0;
+  const double tol = 8.0 * (std::nextafter(q[nq - 1], INFINITY) - q[nq - 1]);
+  for (int32_t m = 1; m + 1 < nq; ++m) {
+    const double dev = std::fabs(q[m] - (a + m * d));
+    if (dev > tol) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] deviates from a uniform grid by %g", m, dev);
+  }
+  if (q0) *q0 = a;
+  if (dq) *dq = d;
+  return SAS_OK;
+}
+
+sas_status sas_create(int device, sas_ctx** out) {
+  if (!out) return fail(SAS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return fail(SAS_ERR_HIP, "hipGetDeviceCount: %s", hipGetErrorString(e));
+  if (device < 0 || device >= count) return fail(SAS_ERR_INVALID_ARG, "device %d not in [0, %d)", device, count);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return fail(SAS_ERR_HIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SAS_ERR_INVALID_ARG, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+  sas_ctx* c = new (std::nothrow) sas_ctx();
+  if (!c) return fail(SAS_ERR_OUT_OF_MEMORY, "context allocation failed");
+  c->device = device;
+  c->cu_count = prop.multiProcessorCount;
+  *out = c;
+  return SAS_OK;
+}
+
+void sas_destroy(sas_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard g(ctx->device);
+    for (auto* v : {&ctx->ev_fwd, &ctx->ev_adj})
+      for (auto& p : *v) {
+        (void)hipEventSynchronize(p.second);
+        ctx->ev_pool.push_back(p.first);
+        ctx->ev_pool.push_back(p.second);
+      }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->pinned_ev) {
+      (void)hipEventSynchronize(ctx->pinned_ev);
+      (void)hipEventDestroy(ctx->pinned_ev);
+    }
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  }
+  delete ctx;
+}
+
+sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  if (bj != 0 && !sas::forward_bj_supported(bj)) return fail(SAS_ERR_INVALID_ARG, "unsupported bj %d", bj);
+  if (qc != 0 && !sas::forward_qc_supported(qc)) return fail(SAS_ERR_INVALID_ARG, "unsupported qc %d", qc);
+  ctx->force_bj = bj;
+  ctx->force_qc = qc;
+  return SAS_OK;
+}
+
+sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc) {
+  if (!ctx || !bj || !qc) return fail(SAS_ERR_INVALID_ARG, "NULL argument");
+  *bj = ctx->last_bj;
+  *qc = ctx->last_qc;
+  return SAS_OK;
+}
+
+sas_status sas_enable_timing(sas_ctx* ctx, int on) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  ctx->timing = on != 0;
+  return SAS_OK;
+}
+
+sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_launches, double* adjoint_ms,
+                           int64_t* adjoint_launches) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  double sums[2] = {0.0, 0.0};
+  int64_t counts[2] = {0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* recs[2] = {&ctx->ev_fwd, &ctx->ev_adj};
+  sas_status st = SAS_OK;
+  for (int k = 0; k < 2; ++k) {
+    for (auto& p : *recs[k]) {
+      float ms = 0.f;
+      if (st == SAS_OK) {
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess) st = fail(SAS_ERR_HIP, "event timing: %s", hipGetErrorString(e));
+      }
+      sums[k] += ms;
+      counts[k] += 1;
+      ctx->ev_pool.push_back(p.first);
+      ctx->ev_pool.push_back(p.second);
+    }
+    recs[k]->clear();
+  }
+  if (forward_ms) *forward_ms = sums[0];
+  if (forward_launches) *forward_launches = counts[0];
+  if (adjoint_ms) *adjoint_ms = sums[1];
+  if (adjoint_launches) *adjoint_launches = counts[1];
+  return st;
+}
+
+size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
+  if (check_sizes(n, t, nq) != SAS_OK) return 0;
+  (void)grad;
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  return make_layout(sc, t, nq).total;
+}
+
+sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
+                             int32_t t, const double* q, int32_t nq, double* I_out, void* workspace, size_t ws_bytes,
+                             void* stream) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  sas_status st = check_sizes(n, t, nq);
+  if (st != SAS_OK) return st;
+  if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
+  double q0 = 0, dq = 0;
+  st = sas_q_grid_check(q, nq, &q0, &dq);
+  if (st != SAS_OK) return st;
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  const Layout L = make_layout(sc, t, nq);
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace,
+                       static_cast<hipStream_t>(stream));
+  if (st == SAS_OK) {
+    ctx->last_bj = sc.geo.bj;
+    ctx->last_qc = sc.qc_template;
+  }
+  return st;
+}
+
+size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offsets, int32_t S, int32_t t,
+                                        int32_t nq) {
+  std::vector<int64_t> sizes;
+  if (check_offsets(offsets, S, &sizes) != SAS_OK) return 0;
+  if (check_sizes(0, t, nq) != SAS_OK) return 0;
+  const Schedule sc = make_schedule(ctx, sizes, t, nq);
+  return make_layout(sc, t, nq).total;
+}
+
+sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const int32_t* types,
+                                     const int64_t* offsets, int32_t S, const float* table, int32_t t,
+                                     const double* q, int32_t nq, double* I_out, void* workspace, size_t ws_bytes,
+                                     void* stream) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  std::vector<int64_t> sizes;
+  sas_status st = check_offsets(offsets, S, &sizes);
+  if (st != SAS_OK) return st;
+  st = check_sizes(0, t, nq);
+  if (st != SAS_OK) return st;
+  if (offsets[S] > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || (S > 0 && !I_out)) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
+  double q0 = 0, dq = 0;
+  st = sas_q_grid_check(q, nq, &q0, &dq);
+  if (st != SAS_OK) return st;
+  if (S == 0) return SAS_OK;
+  const Schedule sc = make_schedule(ctx, sizes, t, nq);
+  const Layout L = make_layout(sc, t, nq);
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (sc.S > 1) {
+    const size_t bytes = sizeof(StructDesc) * sc.S;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (ctx->pinned_used) SAS_HIP(hipEventSynchronize(ctx->pinned_ev));
+    if (ctx->pinned_bytes < bytes) {
+      if (ctx->pinned) SAS_HIP(hipHostFree(ctx->pinned));
+      ctx->pinned = nullptr;
+      ctx->pinned_bytes = 0;
+      if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(SAS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes failed", bytes);
+      ctx->pinned_bytes = bytes;
+    }
+    if (!ctx->pinned_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+    std::memcpy(ctx->pinned, sc.desc.data(), bytes);
+    SAS_HIP(hipMemcpyAsync(static_cast<char*>(workspace) + L.desc, ctx->pinned, bytes, hipMemcpyHostToDevice, hs));
+    SAS_HIP(hipEventRecord(ctx->pinned_ev, hs));
+    ctx->pinned_used = true;
+  }
+  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace, hs);
+  if (st == SAS_OK) {
+    ctx->last_bj = sc.geo.bj;
+    ctx->last_qc = sc.qc_template;
+  }
+  return st;
+}
+
+sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int32_t* types, const int64_t* offsets,
+                                   int32_t S, const float* table, int32_t t, const double* q, int32_t nq,
+                                   double* I_out, void* workspace, size_t ws_bytes, sas_plan** out) {
+  (void)ctx; (void)coords; (void)types; (void)offsets; (void)S; (void)table; (void)t; (void)q; (void)nq;
+  (void)I_out; (void)workspace; (void)ws_bytes;
+  if (out) *out = nullptr;
+  return fail(SAS_ERR_UNSUPPORTED, "plans are not available in this build");
+}
+
+sas_status sas_plan_execute(sas_plan* plan, void* stream) {
+  (void)plan; (void)stream;
+  return fail(SAS_ERR_UNSUPPORTED, "plans are not available in this build");
+}
+
+void sas_plan_destroy(sas_plan* plan) { (void)plan; }
+
+sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
+                          int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
+                          double* I_out, void* workspace, size_t ws_bytes, void* stream) {
+  (void)ctx; (void)coords; (void)types; (void)n; (void)table; (void)t; (void)q; (void)nq; (void)dL_dI;
+  (void)grad_out; (void)I_out; (void)workspace; (void)ws_bytes; (void)stream;
+  return fail(SAS_ERR_UNSUPPORTED, "the gradient is not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Device-side helpers shared by the Debye kernels (gfx950).
+//
+// FP64 trigonometry for the per-pair set-up of the q recurrence.  The set-up
+// runs once per atom pair and q chunk, the recurrence itself runs in FP32, so
+// these helpers favour clear, branch-free FP64 code over speed:
+//   * sin/cos on |x| <= pi/4 by their Taylor series in Horner form;
+//   * additive range reduction by Cody & Waite (1980) with pi/2 and pi split
+//     into three parts of 33 significant bits each, so k * part is exact for
+//     |k| < 2^20 (|argument| < 1.6e6 rad).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sas {
+
+// pi/2 = kPio2A + kPio2B + kPio2C (each part rounded to 33 bits); pi = 2 x that.
+constexpr double kPio2A = 0x1.921fb54400000p+0;
+constexpr double kPio2B = 0x1.0b4611a600000p-34;
+constexpr double kPio2C = 0x1.3198a2e037073p-69;
+constexpr double kPiA = 0x1.921fb54400000p+1;
+constexpr double kPiB = 0x1.0b4611a600000p-33;
+constexpr double kPiC = 0x1.3198a2e037073p-68;
+constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
+constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
+
+// 1/n! for the Taylor coefficients (n! is exact in FP64 up to 22!).
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+
+struct SinCos {
+  double s, c;
+};
+
+// Taylor coefficients, evaluated at compile time.  Terms through x^11 (sin)
+// and x^12 (cos) leave a truncation below 1e-11 relative for |x| <= pi/4;
+// every value derived from them is rounded to FP32 (6e-8) afterwards, so the
+// truncation adds no measurable bias.
+constexpr double kS3 = -1.0 / fact(3), kS5 = 1.0 / fact(5), kS7 = -1.0 / fact(7), kS9 = 1.0 / fact(9);
+constexpr double kS11 = -1.0 / fact(11);
+constexpr double kC2 = -1.0 / fact(2), kC4 = 1.0 / fact(4), kC6 = -1.0 / fact(6), kC8 = 1.0 / fact(8);
+constexpr double kC10 = -1.0 / fact(10), kC12 = 1.0 / fact(12);
+
+// a * b + c with the constant c taken from an SGPR pair.  Written as inline
+// assembly because the compiler otherwise keeps every FP64 polynomial
+// coefficient in a VGPR pair, which costs the forward kernel its second wave
+// per SIMD.
+__device__ __forceinline__ double fma_vvs(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+__device__ __forceinline__ double mul_vs(double a, double b) {
+  double r;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+__device__ __forceinline__ double add_vs(double a, double b) {
+  double r;
+  asm("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(b));
+  return r;
+}
+
+// sin and cos of |x| <= pi/4.
+__device__ __forceinline__ SinCos sincos_small(double x) {
+  const double x2 = x * x;
+  double ps = add_vs(mul_vs(x2, kS11), kS9);
+  ps = fma_vvs(ps, x2, kS7);
+  ps = fma_vvs(ps, x2, kS5);
+  ps = fma_vvs(ps, x2, kS3);
+  double pc = add_vs(mul_vs(x2, kC12), kC10);
+  pc = fma_vvs(pc, x2, kC8);
+  pc = fma_vvs(pc, x2, kC6);
+  pc = fma_vvs(pc, x2, kC4);
+  pc = fma_vvs(pc, x2, kC2);
+  SinCos r;
+  r.s = fma(x * x2, ps, x);
+  r.c = fma(x2, pc, 1.0);
+  return r;
+}
+
+// sin and cos of any |x| < 1.6e6 (quadrant reduction by pi/2).
+__device__ __forceinline__ SinCos sincos_any(double x) {
+  const double k = rint(x * kTwoOverPi);
+  double y = fma(-k, kPio2A, x);
+  y = fma(-k, kPio2B, y);
+  y = fma(-k, kPio2C, y);
+  const SinCos b = sincos_small(y);
+  const int quad = static_cast<int>(static_cast<int64_t>(k) & 3);
+  SinCos r;
+  // x = y + quad * pi/2
+  r.s = (quad & 1) ? b.c : b.s;
+  r.c = (quad & 1) ? b.s : b.c;
+  if (quad == 1 || quad == 2) r.c = -r.c;
+  if (quad & 2) r.s = -r.s;
+  return r;
+}
+
+// 1/sqrt(a) for a > 0 in FP64: hardware estimate refined by two Newton steps
+// (relative error near 1e-16).
+__device__ __forceinline__ double rsqrt_f64(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  const double h = 0.5 * a;
+  y = y * fma(-h, y * y, 1.5);
+  y = y * fma(-h, y * y, 1.5);
+  return y;
+}
+
+}  // namespace sas

@@ -1,0 +1,73 @@
+// Internal interface between the C ABI (sas_api.hip) and the kernels
+// (sas_kernels.hip).  Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sas {
+
+constexpr int kWave = 64;       // wavefront size on gfx950; one wave per forward work-group
+constexpr int kPackBlock = 256; // atoms per block of the pack (type sort) kernels
+constexpr int kSliceTiles = 256;  // strips summed by one first-level reduce work-group
+
+// Per-structure schedule, in execution order (largest structure first).
+struct StructDesc {
+  int64_t atom_off;   // first row of this structure in the concatenated input
+  int64_t strip_off;  // first strip of this structure
+  int64_t slice_off;  // first first-level reduce slice of this structure
+  int32_t n;          // atoms
+  int32_t orig;       // index of the structure in the caller's order (row of I_out)
+  int32_t pack_off;   // first pack block of this structure
+  int32_t n_strips;   // strips of this structure
+  int32_t n_slices;   // reduce slices of this structure
+  int32_t pad;
+};
+
+// A view that carries one descriptor inline (plain call: no upload needed) or
+// points at an array in device memory (batched call).
+struct DescView {
+  const StructDesc* arr;
+  StructDesc one;
+  int32_t S;
+  __device__ __forceinline__ StructDesc get(int s) const { return S == 1 ? one : arr[s]; }
+};
+
+// Tile geometry for one launch: I blocks of kWave atoms, J blocks of bj atoms,
+// strips of up to g J blocks.
+struct Geometry {
+  int32_t bj;  // atoms per J block (multiple of kWave)
+  int32_t c;   // bj / kWave
+  int32_t g;   // J blocks per strip
+};
+
+struct ForwardArgs {
+  DescView sd;
+  Geometry geo;
+  const double4* xyz;   // type-sorted FP64 coordinates (w unused)
+  const int32_t* tsort; // type-sorted type ids
+  const int32_t* toff;  // [S][T+1] absolute start of each type segment (sorted rows)
+  const float* tabp;    // [T][ldt] form factors, zero in columns >= Nq
+  double* partial;      // [strips][Nq]
+  int32_t T, Nq;
+  int32_t ldt;          // row stride of tabp: (chunks-1)*qc + QC
+  int32_t qc;           // q values per chunk (grid.y = number of chunks)
+  double q0, dq;
+};
+
+// Host-side helpers implemented in sas_kernels.hip.
+int64_t strips_of(int64_t n, const Geometry& g);
+int64_t slices_of(int64_t n_strips);
+
+hipError_t launch_pack(const float* coords, const int32_t* types, const DescView& sd, int32_t S,
+                       int64_t n_pack_blocks, int32_t T, int32_t* bcount, int32_t* toff, double4* xyz,
+                       int32_t* tsort, int32_t* perm, hipStream_t st);
+hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st);
+hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
+hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
+                         double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
+                         double q0, double dq, double* I_out, hipStream_t st);
+
+bool forward_qc_supported(int32_t qc);
+bool forward_bj_supported(int32_t bj);
+
+}  // namespace sas

@@ -45,7 +45,7 @@ def write(name: str) -> None:
                  f"({dt:.1f} s on {oracle.max_threads()} threads)\n")
         fh.write("# q  I(q)  A(q)=sum|f f sinc|\n")
         for qm, Im, Am in zip(q, I, A):
-            fh.write(f"{qm!r} {Im!r} {Am!r}\n")
+            fh.write(f"{float(qm)!r} {float(Im)!r} {float(Am)!r}\n")
     print(f"{name}: {dt:.1f} s -> {path}", flush=True)
 
 

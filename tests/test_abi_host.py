@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and its host-only logic (q-grid analysis, size queries, status
+strings) behaves as documented.  No device work is issued here."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sas_debye.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1306_2258_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1306_2258_amd import build
+
+        build.build()
+    return _lib.load()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sas_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_three_entry_points():
+    names = declared_symbols()
+    for n in ("sas_debye_profile", "sas_debye_profile_batched", "sas_debye_grad"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1306_2258_amd import _lib
+
+    for name in declared_symbols():
+        assert hasattr(lib, name), f"{name} not exported"
+        assert name in _lib.SIGNATURES, f"{name} has no ctypes signature in the binding"
+
+
+def test_version_and_status_strings(lib):
+    assert lib.sas_version() >= 100
+    assert lib.sas_status_string(0) == b"SAS_OK"
+    assert lib.sas_status_string(2) == b"SAS_ERR_Q_NOT_UNIFORM"
+
+
+def _grid(lib, q):
+    q = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    q0 = ctypes.c_double()
+    dq = ctypes.c_double()
+    st = lib.sas_q_grid_check(q.ctypes.data_as(ctypes.c_void_p), len(q), ctypes.byref(q0), ctypes.byref(dq))
+    return st, q0.value, dq.value
+
+
+def test_q_grid_uniform(lib):
+    st, q0, dq = _grid(lib, np.linspace(0.0, 1.0, 200))
+    assert st == 0 and q0 == 0.0 and abs(dq - 1.0 / 199) < 1e-18
+    st, q0, dq = _grid(lib, np.arange(1, 51) / 50.0)  # the paper's 0 < q <= 1 grid
+    assert st == 0 and q0 == 0.02
+    st, q0, dq = _grid(lib, [0.3])
+    assert st == 0 and q0 == 0.3 and dq == 0.0
+
+
+@pytest.mark.parametrize("bad", [
+    [0.0, 0.1, 0.25, 0.3],        # not uniform
+    [0.0, 0.2, 0.1],              # decreasing
+    [0.1, 0.1, 0.2],              # repeated
+    [-0.1, 0.0, 0.1],             # negative
+    [0.0, float("nan"), 0.2],     # not finite
+    [0.0, 0.1, float("inf")],
+])
+def test_q_grid_rejects(lib, bad):
+    st, _, _ = _grid(lib, bad)
+    assert st == 2
+    assert lib.sas_last_error()
+
+
+def test_q_grid_tolerates_rounding(lib):
+    q = np.linspace(0.0, 0.8, 100)
+    q[37] = np.nextafter(q[37], 1.0)
+    assert _grid(lib, q)[0] == 0
+
+
+def test_q_grid_null_and_sizes(lib):
+    assert lib.sas_q_grid_check(None, 5, None, None) == 1
+    q = np.zeros(1)
+    assert lib.sas_q_grid_check(q.ctypes.data_as(ctypes.c_void_p), 0, None, None) == 1
+
+
+def test_workspace_queries(lib):
+    a = lib.sas_debye_workspace_size(None, 50000, 5, 200, 0)
+    b = lib.sas_debye_workspace_size(None, 1000, 5, 64, 0)
+    assert a > b > 0
+    assert lib.sas_debye_workspace_size(None, -1, 5, 64, 0) == 0
+    assert lib.sas_debye_workspace_size(None, 10, 0, 64, 0) == 0
+    assert lib.sas_debye_workspace_size(None, 10, 5, 0, 0) == 0
+    assert lib.sas_debye_workspace_size(None, 10, 5000, 8, 0) == 0  # T above the limit
+    off = np.array([0, 500, 8500, 9000], dtype=np.int64)
+    assert lib.sas_debye_workspace_size_batched(None, off.ctypes.data_as(ctypes.c_void_p), 3, 5, 100) > 0
+    bad = np.array([0, 500, 400], dtype=np.int64)
+    assert lib.sas_debye_workspace_size_batched(None, bad.ctypes.data_as(ctypes.c_void_p), 2, 5, 100) == 0
+
+
+def test_calls_without_context_fail_cleanly(lib):
+    q = np.linspace(0, 1, 4)
+    st = lib.sas_debye_profile(None, None, None, 0, None, 1, q.ctypes.data_as(ctypes.c_void_p), 4, None, None, 0,
+                               None)
+    assert st == 1
+    assert b"ctx" in lib.sas_last_error()
+
+
+def test_binding_raises_without_gpu_tensors():
+    import torch
+
+    import paper_1306_2258_amd as sd
+
+    with pytest.raises(ValueError):
+        sd.debye_profile(torch.zeros(3, 3), torch.zeros(3, dtype=torch.int32), torch.zeros(1, 4), [0, 1, 2, 3])
+
+
+def test_binding_q_grid_check():
+    import paper_1306_2258_amd as sd
+
+    assert sd.q_grid_check([0.0, 0.5, 1.0]) == (0.0, 0.5)
+    with pytest.raises(sd.SasError) as e:
+        sd.q_grid_check([0.0, 0.5, 1.1])
+    assert e.value.status == 2
