@@ -231,14 +231,21 @@ def test_batched_matches_plain_and_oracle(sd):
     off[1:] = np.cumsum(sizes)
     out = sd.debye_profile_batched(torch.from_numpy(coords).cuda(), torch.from_numpy(types).cuda(), off,
                                    torch.from_numpy(table).cuda(), mols[0].q).cpu().numpy()
+    # with one tile shape forced for both, a structure's batched result is the
+    # plain call's result bit for bit (same tiles, same summation order)
+    ctx = sd.Context(0)
+    ctx.set_variant(128, 32)
+    out_forced = sd.debye_profile_batched(torch.from_numpy(coords).cuda(), torch.from_numpy(types).cuda(), off,
+                                          torch.from_numpy(table).cuda(), mols[0].q, ctx=ctx).cpu().numpy()
     for k, mm in enumerate(mols):
         ref = oracle.profile(mm.coords, mm.types, table, mm.q)
         if sizes[k] == 0:
-            assert np.all(out[k] == 0.0)
+            assert np.all(out[k] == 0.0) and np.all(out_forced[k] == 0.0)
             continue
         assert rel_err(out[k], ref).max() <= TOL, f"structure {k} (N={sizes[k]})"
-        plain = gpu_profile(sd, W.Molecule("p", mm.coords, mm.types, table, mm.q))
-        assert rel_err(out[k], plain).max() <= 1e-9
+        assert rel_err(out_forced[k], ref).max() <= TOL, f"structure {k} (N={sizes[k]}), forced variant"
+        plain = gpu_profile(sd, W.Molecule("p", mm.coords, mm.types, table, mm.q), ctx=ctx)
+        assert np.array_equal(out_forced[k], plain), f"structure {k}"
 
 
 def test_batched_single_structure_equals_plain(sd):
