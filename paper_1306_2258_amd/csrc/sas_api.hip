@@ -116,6 +116,11 @@ struct Schedule {
   Geometry geo{};
   int32_t qc = 0, qc_template = 0;
   int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
+  // adjoint (gradient) schedule, single structure only
+  bool grad = false;
+  Geometry geo_adj{};
+  int64_t n_strips_adj = 0;
+  int32_t qa = 0, nchunks_adj = 0;
   int32_t S = 0;
   int64_t n_total = 0;
   int64_t n_pack = 0, n_strips = 0, n_slices = 0;
@@ -123,7 +128,8 @@ struct Schedule {
 };
 
 struct Layout {
-  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, desc = 0, tabp = 0, partial = 0, slices = 0, total = 0;
+  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, desc = 0, tabp = 0, partial = 0, slices = 0;
+  size_t gI = 0, gJ = 0, total = 0;
 };
 
 int32_t pick_qc_template(int32_t qc) {
@@ -202,6 +208,21 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   return sc;
 }
 
+// Adds the adjoint's strip geometry (J blocks of 128 atoms, one block per
+// strip) and q chunks (<= kAdjQ values each) to a single-structure schedule.
+void add_adjoint(Schedule* sc, int64_t n, int32_t Nq) {
+  sc->grad = true;
+  sc->geo_adj.bj = 128;
+  sc->geo_adj.c = 128 / sas::kWave;
+  sc->geo_adj.g = 1;
+  sc->n_strips_adj = sas::strips_of(n, sc->geo_adj);
+  const int32_t nch = (Nq + sas::kAdjQ - 1) / sas::kAdjQ;
+  int32_t qa = (Nq + nch - 1) / nch;
+  qa = (qa + 7) / 8 * 8;
+  sc->qa = std::min(qa, static_cast<int32_t>(sas::kAdjQ));
+  sc->nchunks_adj = (Nq + sc->qa - 1) / sc->qa;
+}
+
 Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   Layout L;
   size_t p = 0;
@@ -219,6 +240,11 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   L.tabp = take(sizeof(float) * static_cast<size_t>(T) * sc.ldt);
   L.partial = take(sizeof(double) * sc.n_strips * Nq);
   L.slices = take(sizeof(double) * sc.n_slices * Nq);
+  if (sc.grad) {
+    const size_t rows = static_cast<size_t>(sc.nchunks_adj) * sc.n_strips_adj;
+    L.gI = take(sizeof(double) * 3 * rows * sas::kWave);
+    L.gJ = take(sizeof(double) * 3 * rows * sc.geo_adj.g * sc.geo_adj.bj);
+  }
   L.total = p;
   return L;
 }
@@ -431,8 +457,8 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
   if (check_sizes(n, t, nq) != SAS_OK) return 0;
-  (void)grad;
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  if (grad) add_adjoint(&sc, n, nq);
   return make_layout(sc, t, nq).total;
 }
 
@@ -543,9 +569,60 @@ void sas_plan_destroy(sas_plan* plan) { (void)plan; }
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
                           int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
                           double* I_out, void* workspace, size_t ws_bytes, void* stream) {
-  (void)ctx; (void)coords; (void)types; (void)n; (void)table; (void)t; (void)q; (void)nq; (void)dL_dI;
-  (void)grad_out; (void)I_out; (void)workspace; (void)ws_bytes; (void)stream;
-  return fail(SAS_ERR_UNSUPPORTED, "the gradient is not available in this build");
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  sas_status st = check_sizes(n, t, nq);
+  if (st != SAS_OK) return st;
+  if (n > 0 && (!coords || !types || !grad_out)) return fail(SAS_ERR_INVALID_ARG, "coords/types/grad_out is NULL");
+  if (!table || !dL_dI) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI is NULL");
+  double q0 = 0, dq = 0;
+  st = sas_q_grid_check(q, nq, &q0, &dq);
+  if (st != SAS_OK) return st;
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  add_adjoint(&sc, n, nq);
+  const Layout L = make_layout(sc, t, nq);
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+  if (I_out) {
+    st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace, hs);
+    if (st != SAS_OK) return st;
+  } else {
+    SAS_HIP(sas::launch_pad_table(table, t, nq, sc.ldt, reinterpret_cast<float*>(w + L.tabp), hs));
+    SAS_HIP(sas::launch_pack(coords, types, view_of(sc, workspace, L), sc.S, sc.n_pack, t,
+                             reinterpret_cast<int32_t*>(w + L.bcount), reinterpret_cast<int32_t*>(w + L.toff),
+                             reinterpret_cast<double4*>(w + L.xyz), reinterpret_cast<int32_t*>(w + L.tsort),
+                             reinterpret_cast<int32_t*>(w + L.perm), hs));
+  }
+  if (n == 0) return SAS_OK;
+  sas::AdjArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sd = view_of(sc, workspace, L);
+  a.geo = sc.geo_adj;
+  a.xyz = reinterpret_cast<const double4*>(w + L.xyz);
+  a.tsort = reinterpret_cast<const int32_t*>(w + L.tsort);
+  a.toff = reinterpret_cast<const int32_t*>(w + L.toff);
+  a.tabp = reinterpret_cast<const float*>(w + L.tabp);
+  a.ldt = sc.ldt;
+  a.T = t;
+  a.Nq = nq;
+  a.qa = sc.qa;
+  a.w = dL_dI;
+  a.gI = reinterpret_cast<double*>(w + L.gI);
+  a.gJ = reinterpret_cast<double*>(w + L.gJ);
+  a.n_strips = sc.n_strips_adj;
+  a.q0 = q0;
+  a.dq = dq;
+  {
+    LaunchTimer timer(ctx, hs, true);
+    SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));
+  }
+  SAS_HIP(sas::launch_grad_reduce(a, n, sc.nchunks_adj, reinterpret_cast<const int32_t*>(w + L.perm), grad_out, hs));
+  return SAS_OK;
 }
 
 }  // extern "C"

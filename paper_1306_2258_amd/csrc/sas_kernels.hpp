@@ -54,7 +54,26 @@ struct ForwardArgs {
   double q0, dq;
 };
 
-// Host-side helpers implemented in sas_kernels.hip.
+constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
+
+struct AdjArgs {
+  DescView sd;          // one structure
+  Geometry geo;         // adjoint strip geometry
+  const double4* xyz;
+  const int32_t* tsort;
+  const int32_t* toff;  // [T+1]
+  const float* tabp;    // [T][ldt]
+  int32_t ldt;
+  int32_t T, Nq;
+  int32_t qa;           // q values per chunk (<= kAdjQ); grid.y = chunks
+  const double* w;      // dL/dI [Nq]
+  double* gI;           // [chunks][strips][64][3] i-side partial sums
+  double* gJ;           // [chunks][strips][g*bj][3] j-side partial sums
+  int64_t n_strips;
+  double q0, dq;
+};
+
+// Host-side helpers implemented in sas_kernels.hip / sas_adjoint.hip.
 int64_t strips_of(int64_t n, const Geometry& g);
 int64_t slices_of(int64_t n_strips);
 
@@ -67,6 +86,10 @@ hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, 
                          double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
                          double q0, double dq, double* I_out, hipStream_t st);
 
+hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st);
+hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, const int32_t* perm, double* grad_out,
+                              hipStream_t st);
+bool adjoint_bj_supported(int32_t bj);
 bool forward_qc_supported(int32_t qc);
 bool forward_bj_supported(int32_t bj);
 
