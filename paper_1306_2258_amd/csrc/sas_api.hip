@@ -58,8 +58,8 @@ struct sas_ctx {
   hipEvent_t pinned_ev = nullptr;
   bool pinned_used = false;
   std::mutex mu;
-  // tuned (bj) per workload key, filled by plans
-  std::map<std::string, int32_t> tuned_bj;
+  // tile shape (bj, qc) chosen by timing, per workload key; filled by plans
+  std::map<std::string, std::pair<int32_t, int32_t>> tuned;
   // optional kernel timing: event pairs around pair-kernel launches
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
@@ -146,7 +146,7 @@ int32_t default_bj(int64_t max_n) {
 
 // Build the schedule for structure sizes `sizes` (caller order).
 Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
-                       int32_t bj_override = 0) {
+                       int32_t bj_override = 0, int32_t qc_override = 0) {
   Schedule sc;
   sc.S = static_cast<int32_t>(sizes.size());
   int64_t max_n = 0;
@@ -156,7 +156,11 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   }
   // q chunking: one chunk up to 200 values, else balanced chunks of <= 200
   int32_t qc = Nq;
-  if (ctx && ctx->force_qc > 0) {
+  if (qc_override > 0) {
+    const int32_t nch = (Nq + qc_override - 1) / qc_override;
+    qc = (Nq + nch - 1) / nch;
+    sc.qc_template = pick_qc_template(qc);
+  } else if (ctx && ctx->force_qc > 0) {
     qc = std::min(ctx->force_qc, Nq);
     sc.qc_template = ctx->force_qc;
   } else {
@@ -206,6 +210,35 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   sc.n_slices = slice;
   sc.n_pack = pack;
   return sc;
+}
+
+// Tile shapes a plan may time: every J-block size, with the default q chunk
+// and (where a smaller template exists) half of it.  A forced variant is the
+// only candidate.
+std::vector<std::pair<int32_t, int32_t>> tile_candidates(const sas_ctx* ctx, int32_t Nq) {
+  std::vector<std::pair<int32_t, int32_t>> out;
+  if (ctx && (ctx->force_bj > 0 || ctx->force_qc > 0)) {
+    out.emplace_back(ctx->force_bj, ctx->force_qc);
+    return out;
+  }
+  const int32_t nch = (Nq + 199) / 200;
+  const int32_t qdef = pick_qc_template((Nq + nch - 1) / nch);
+  std::vector<int32_t> qcs{qdef};
+  if (qdef >= 100 && Nq > 50) qcs.push_back(qdef / 2);
+  for (int32_t bj : {64, 128, 256, 512})
+    for (int32_t qc : qcs) out.emplace_back(bj, qc == qdef ? 0 : qc);
+  return out;
+}
+
+std::string workload_key(const std::vector<int64_t>& sizes, int32_t T, int32_t Nq) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the sizes
+  for (int64_t n : sizes) {
+    h ^= static_cast<uint64_t>(n);
+    h *= 1099511628211ull;
+  }
+  char buf[128];
+  snprintf(buf, sizeof(buf), "S%zu:T%d:Q%d:%016llx", sizes.size(), T, Nq, static_cast<unsigned long long>(h));
+  return buf;
 }
 
 // Adds the adjoint's strip geometry (J blocks of 128 atoms, one block per
@@ -495,8 +528,11 @@ size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offse
   std::vector<int64_t> sizes;
   if (check_offsets(offsets, S, &sizes) != SAS_OK) return 0;
   if (check_sizes(0, t, nq) != SAS_OK) return 0;
-  const Schedule sc = make_schedule(ctx, sizes, t, nq);
-  return make_layout(sc, t, nq).total;
+  // large enough for the automatic shape and for every shape a plan may time
+  size_t need = make_layout(make_schedule(ctx, sizes, t, nq), t, nq).total;
+  for (const auto& c : tile_candidates(ctx, nq))
+    need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second), t, nq).total);
+  return need;
 }
 
 sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const int32_t* types,
@@ -550,21 +586,182 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   return st;
 }
 
+}  // extern "C"
+
+struct sas_plan {
+  sas_ctx* ctx = nullptr;
+  std::vector<int64_t> sizes;
+  const float* coords = nullptr;
+  const int32_t* types = nullptr;
+  const float* table = nullptr;
+  double* I_out = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int32_t T = 0, Nq = 0;
+  double q0 = 0, dq = 0;
+  Schedule sc;
+  Layout L;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool ready = false;
+};
+
+namespace {
+
+sas_status upload_desc(const Schedule& sc, const Layout& L, void* ws) {
+  if (sc.S > 1)
+    SAS_HIP(hipMemcpy(static_cast<char*>(ws) + L.desc, sc.desc.data(), sizeof(StructDesc) * sc.S,
+                      hipMemcpyHostToDevice));
+  return SAS_OK;
+}
+
+// Times every candidate tile shape on the plan's own buffers (one warm-up and
+// two timed evaluations each, HIP events on `st`) and returns the fastest.
+sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
+  const auto cands = tile_candidates(p->ctx, p->Nq);
+  float best = -1.f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SAS_HIP(hipEventCreate(&e0));
+  SAS_HIP(hipEventCreate(&e1));
+  sas_status status = SAS_OK;
+  for (const auto& c : cands) {
+    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second);
+    const Layout L = make_layout(sc, p->T, p->Nq);
+    if (L.total > p->ws_bytes) continue;
+    status = upload_desc(sc, L, p->ws);
+    if (status != SAS_OK) break;
+    status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+                             p->ws, st);
+    if (status != SAS_OK) break;
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && status == SAS_OK; ++r)
+      status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+                               p->ws, st);
+    (void)hipEventRecord(e1, st);
+    if (status != SAS_OK) break;
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      status = fail(SAS_ERR_HIP, "tuning timer: %s", hipGetErrorString(e));
+      break;
+    }
+    if (best < 0.f || ms < best) {
+      best = ms;
+      *bj = sc.geo.bj;
+      *qc = c.second;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == SAS_OK && best < 0.f) status = fail(SAS_ERR_WORKSPACE_TOO_SMALL, "no tile shape fits the workspace");
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
 sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int32_t* types, const int64_t* offsets,
                                    int32_t S, const float* table, int32_t t, const double* q, int32_t nq,
                                    double* I_out, void* workspace, size_t ws_bytes, sas_plan** out) {
-  (void)ctx; (void)coords; (void)types; (void)offsets; (void)S; (void)table; (void)t; (void)q; (void)nq;
-  (void)I_out; (void)workspace; (void)ws_bytes;
-  if (out) *out = nullptr;
-  return fail(SAS_ERR_UNSUPPORTED, "plans are not available in this build");
+  if (!out) return fail(SAS_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  std::vector<int64_t> sizes;
+  sas_status st = check_offsets(offsets, S, &sizes);
+  if (st != SAS_OK) return st;
+  st = check_sizes(0, t, nq);
+  if (st != SAS_OK) return st;
+  if (S == 0) return fail(SAS_ERR_INVALID_ARG, "a plan needs at least one structure");
+  if (offsets[S] > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
+  double q0 = 0, dq = 0;
+  st = sas_q_grid_check(q, nq, &q0, &dq);
+  if (st != SAS_OK) return st;
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  const Schedule sc0 = make_schedule(ctx, sizes, t, nq);
+  const size_t need = make_layout(sc0, t, nq).total;
+  if (ws_bytes < need) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, need);
+  sas_plan* p = new (std::nothrow) sas_plan();
+  if (!p) return fail(SAS_ERR_OUT_OF_MEMORY, "plan allocation failed");
+  p->ctx = ctx;
+  p->sizes = sizes;
+  p->coords = coords;
+  p->types = types;
+  p->table = table;
+  p->I_out = I_out;
+  p->ws = workspace;
+  p->ws_bytes = ws_bytes;
+  p->T = t;
+  p->Nq = nq;
+  p->q0 = q0;
+  p->dq = dq;
+  *out = p;
+  return SAS_OK;
 }
 
-sas_status sas_plan_execute(sas_plan* plan, void* stream) {
-  (void)plan; (void)stream;
-  return fail(SAS_ERR_UNSUPPORTED, "plans are not available in this build");
+sas_status sas_plan_execute(sas_plan* p, void* stream) {
+  if (!p) return fail(SAS_ERR_INVALID_ARG, "plan is NULL");
+  DeviceGuard g(p->ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", p->ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  if (!p->ready) {
+    // choose the tile shape: forced variant, cached choice, or timing
+    int32_t bj = 0, qc = 0;
+    const std::string key = workload_key(p->sizes, p->T, p->Nq);
+    const bool forced = p->ctx->force_bj > 0 || p->ctx->force_qc > 0;
+    auto it = p->ctx->tuned.find(key);
+    if (forced) {
+      bj = p->ctx->force_bj;
+    } else if (it != p->ctx->tuned.end()) {
+      bj = it->second.first;
+      qc = it->second.second;
+    } else {
+      sas_status st = tune_plan(p, hs, &bj, &qc);
+      if (st != SAS_OK) return st;
+      p->ctx->tuned[key] = {bj, qc};
+    }
+    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc);
+    p->L = make_layout(p->sc, p->T, p->Nq);
+    if (p->L.total > p->ws_bytes)
+      return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", p->ws_bytes, p->L.total);
+    sas_status st = upload_desc(p->sc, p->L, p->ws);
+    if (st != SAS_OK) return st;
+    // capture pack -> pair kernel -> reduce on a private stream
+    if (!p->cap) SAS_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+    SAS_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+    st = enqueue_forward(nullptr, p->sc, p->L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+                         p->ws, p->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap, &graph);
+    if (st != SAS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(SAS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    p->graph = graph;
+    SAS_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    p->ready = true;
+    p->ctx->last_bj = p->sc.geo.bj;
+    p->ctx->last_qc = p->sc.qc_template;
+  }
+  SAS_HIP(hipGraphLaunch(p->exec, hs));
+  return SAS_OK;
 }
 
-void sas_plan_destroy(sas_plan* plan) { (void)plan; }
+void sas_plan_destroy(sas_plan* p) {
+  if (!p) return;
+  {
+    DeviceGuard g(p->ctx->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+  }
+  delete p;
+}
 
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
                           int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,

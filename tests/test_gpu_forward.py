@@ -281,3 +281,78 @@ def test_errors_are_reported(sd):
                                ctypes.c_void_p(tab.data_ptr()), 5, qh.ctypes.data_as(ctypes.c_void_p), 5,
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), 256, None)
     assert st == 4  # workspace too small
+
+
+# ---------------------------------------------------------------------------
+# Batched plan: tuned tile shape, captured graph, replays after in-place updates
+# ---------------------------------------------------------------------------
+
+def _ensemble(sizes, seed=3000, nq=40):
+    mols = [W.random_molecule(seed + k, n, nq, q0=0.0, q1=0.8, extent=2.5 * max(n, 1) ** (1 / 3) + 3)
+            for k, n in enumerate(sizes)]
+    coords = np.concatenate([mm.coords for mm in mols]).astype(np.float32)
+    types = np.concatenate([mm.types for mm in mols]).astype(np.int32)
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return mols, coords, types, off
+
+
+def test_plan_replays_match_eager_and_oracle(sd):
+    import torch
+
+    say("batched plan: tune, capture, replay x3 with in-place coordinate updates")
+    sizes = [900, 130, 2, 1, 0, 2100, 640, 65]
+    mols, coords, types, off = _ensemble(sizes)
+    table, q = mols[0].table, mols[0].q
+    ctx = sd.Context(0)
+    c = torch.from_numpy(coords).cuda()
+    t = torch.from_numpy(types).cuda()
+    tab = torch.from_numpy(table).cuda()
+    plan = sd.BatchedPlan(c, t, off, tab, q, ctx=ctx)
+    rng = np.random.default_rng(11)
+    for rep in range(3):
+        got = plan.execute().clone()
+        torch.cuda.synchronize()
+        bj, qc = ctx.variant()
+        # eager work between replays: an eager batched call with the same shape
+        ctx2 = sd.Context(0)
+        ctx2.set_variant(bj, qc)
+        eager = sd.debye_profile_batched(c, t, off, tab, q, ctx=ctx2)
+        torch.cuda.synchronize()
+        assert torch.equal(got, eager), f"replay {rep} differs from the eager call"
+        host = c.cpu().numpy()
+        for k, n in enumerate(sizes):
+            if n == 0:
+                assert torch.all(got[k] == 0)
+                continue
+            ref = oracle.profile(host[off[k]:off[k + 1]], types[off[k]:off[k + 1]], table, q)
+            assert rel_err(got[k].cpu().numpy(), ref).max() <= TOL, f"replay {rep} structure {k}"
+        # rewrite the coordinates in place: rotate and shift every structure
+        qm, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        new = (host.astype(np.float64) @ qm.T + rng.normal(size=3)).astype(np.float32)
+        new[: off[1]] += rng.normal(scale=0.3, size=(off[1], 3)).astype(np.float32)  # change one structure's shape
+        c.copy_(torch.from_numpy(new).cuda())
+        torch.cuda.synchronize()
+    plan.close()
+
+
+def test_plan_reuses_tuned_shape(sd):
+    import torch
+
+    say("batched plan: second plan of the same workload reuses the tuned shape")
+    sizes = [300, 1200, 77]
+    mols, coords, types, off = _ensemble(sizes, seed=3100, nq=25)
+    ctx = sd.Context(0)
+    c = torch.from_numpy(coords).cuda()
+    t = torch.from_numpy(types).cuda()
+    tab = torch.from_numpy(mols[0].table).cuda()
+    p1 = sd.BatchedPlan(c, t, off, tab, mols[0].q, ctx=ctx)
+    a = p1.execute().clone()
+    v1 = ctx.variant()
+    p2 = sd.BatchedPlan(c, t, off, tab, mols[0].q, ctx=ctx)
+    b = p2.execute().clone()
+    torch.cuda.synchronize()
+    assert ctx.variant() == v1
+    assert torch.equal(a, b)
+    p1.close()
+    p2.close()
