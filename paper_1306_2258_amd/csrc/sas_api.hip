@@ -139,6 +139,7 @@ int32_t pick_qc_template(int32_t qc) {
 }
 
 int32_t default_bj(int64_t max_n) {
+  if (max_n >= 16384) return 512;
   if (max_n >= 2048) return 256;
   if (max_n >= 512) return 128;
   return 64;

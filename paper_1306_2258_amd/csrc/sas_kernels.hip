@@ -163,6 +163,41 @@ hipError_t launch_pack(const float* coords, const int32_t* types, const DescView
 // z += d and d += -lambda z.  Coincident atoms (r = 0) use r^2 = 1e-60, for
 // which the same formulas give the sinc limit y_m = q_m.
 // ---------------------------------------------------------------------------
+// FP32 start of one pair's recurrence: z_0, d_0, -lambda and sigma (see
+// above), from the FP64 set-up.  `use` = 0 gives an all-zero sequence.
+struct PairSeed {
+  float z, d, nlam, sg;
+};
+
+__device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& pj, bool use, double dq, double qs) {
+  const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+  double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  r2 = fmax(r2, 1e-60);
+  const double ir = rsqrt_f64(r2);
+  const double r = r2 * ir;
+  const double delta = dq * r;
+  const double k = rint(delta * kOneOverPi);
+  double dp = fma(-k, kPiA, delta);
+  dp = fma(-k, kPiB, dp);
+  dp = fma(-k, kPiC, dp);
+  const SinCos hh = sincos_small(0.5 * dp);
+  const double sdp = 2.0 * hh.s * hh.c;  // sin(dp)
+  const double omc = 2.0 * hh.s * hh.s;  // 1 - cos(dp) = lambda / 2
+  const double w = use ? ir : 0.0;
+  double S0 = 0.0, C0 = w;
+  if (qs != 0.0) {
+    const SinCos t0 = sincos_any(qs * r);
+    S0 = t0.s * w;
+    C0 = t0.c * w;
+  }
+  PairSeed p;
+  p.z = static_cast<float>(S0);
+  p.d = static_cast<float>(fma(C0, sdp, -S0 * omc));
+  p.nlam = static_cast<float>(-2.0 * omc);
+  p.sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
+  return p;
+}
+
 // Sum acc[0..64) over the 64 lanes; lane l receives the total of element l.
 // Recursive halving: at the step for lane bit b the lane keeps the half of its
 // live range selected by b and adds the partner's copy of that half.
@@ -197,7 +232,7 @@ __device__ __forceinline__ float lane_allreduce_tail(float* acc, int lane) {
 }
 
 template <int QC, int BJ>
-__global__ __launch_bounds__(kWave) void k_forward(ForwardArgs a) {
+__global__ __launch_bounds__(kWave, 2) void k_forward(ForwardArgs a) {
   constexpr int NG = QC / kWave;          // full groups of 64 q values
   constexpr int R = QC % kWave;           // values in the tail group
   constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
@@ -254,41 +289,33 @@ __global__ __launch_bounds__(kWave) void k_forward(ForwardArgs a) {
       float acc[QC];
 #pragma unroll
       for (int m = 0; m < QC; ++m) acc[m] = 0.f;
+      // two atom pairs (j, j+1) per iteration: two independent recurrence
+      // chains give the scheduler work to issue while either waits on its
+      // previous result; an odd segment ends with a masked partner
 #pragma unroll 1
-      for (int jl = sa; jl < sb; ++jl) {
-        const double4 pj = sj[jl - j0];
-        const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-        double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-        r2 = fmax(r2, 1e-60);
-        const double ir = rsqrt_f64(r2);
-        const double r = r2 * ir;
-        const double delta = dq * r;
-        const double k = rint(delta * kOneOverPi);
-        double dp = fma(-k, kPiA, delta);
-        dp = fma(-k, kPiB, dp);
-        dp = fma(-k, kPiC, dp);
-        const SinCos hh = sincos_small(0.5 * dp);
-        const double sdp = 2.0 * hh.s * hh.c;   // sin(dp)
-        const double omc = 2.0 * hh.s * hh.s;   // 1 - cos(dp) = lambda / 2
-        const float nlam = static_cast<float>(-2.0 * omc);
-        const float sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
-        const double w = (vi && jl > i) ? ir : 0.0;
-        double S0 = 0.0, C0 = w;
-        if (qs != 0.0) {
-          const SinCos t0 = sincos_any(qs * r);
-          S0 = t0.s * w;
-          C0 = t0.c * w;
-        }
-        float z = static_cast<float>(S0);
-        float dd = static_cast<float>(fma(C0, sdp, -S0 * omc));
+      for (int jl = sa; jl < sb; jl += 2) {
+        const int jb = jl + 1 < sb ? jl + 1 : jl;
+        // (empty volatile asm: a scheduling boundary, so the two FP64 set-ups
+        // run one after the other and their temporaries never coexist with
+        // each other and the QC accumulators)
+        const PairSeed A = pair_seed(pi, sj[jl - j0], vi && jl > i, dq, qs);
+        asm volatile("" ::: "memory");
+        const PairSeed B = pair_seed(pi, sj[jb - j0], vi && jb > i && jl + 1 < sb, dq, qs);
+        asm volatile("" ::: "memory");
+        float za = A.z, da = A.d, zb = B.z, db = B.d;
 #pragma unroll
         for (int m = 0; m < QC; ++m) {
-          if (m & 1)
-            acc[m] = fmaf(sg, z, acc[m]);
-          else
-            acc[m] += z;
-          z += dd;
-          dd = fmaf(nlam, z, dd);
+          if (m & 1) {
+            acc[m] = fmaf(A.sg, za, acc[m]);
+            acc[m] = fmaf(B.sg, zb, acc[m]);
+          } else {
+            acc[m] += za;
+            acc[m] += zb;
+          }
+          za += da;
+          zb += db;
+          da = fmaf(A.nlam, za, da);
+          db = fmaf(B.nlam, zb, db);
         }
       }
       // weight by this lane's f_a(q_m), sum over lanes, weight by f_b(q_m) in FP64
