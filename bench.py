@@ -32,6 +32,45 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, 256 CU x 2.4 GHz x 256 flop/clk
 FLOPS_PER_PAIR_Q = 10.0   # forward: 4 FMA rotation + 1 FMA accumulate (the metric's convention)
 FLOPS_PER_PAIR_Q_ADJ = 12.0
+# What the forward pair loop really issues per pair*q: v_add_f32 x2 + v_fmac_f32 x1
+# (4 flops), and the issue cost of that mix measured on MI355X with a
+# microbenchmark: 2.3 cycles per wave64 instruction (1024 SIMDs, 2.4 GHz).
+INSTR_PER_PAIR_Q = 3
+EXEC_FLOPS_PER_PAIR_Q = 4.0
+MIX_CYCLES_PER_WAVE_INSTR = 2.3
+ISSUE_CEILING_PAIR_Q = 1024 * 2.4e9 * 64 / (INSTR_PER_PAIR_Q * MIX_CYCLES_PER_WAVE_INSTR)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1306_2258_amd", "csrc", f)
+                  for f in ("sas_kernels.hip", "sas_device.hpp", "sas_schedule.hpp", "sas_kernels.hpp")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_name: str):
+    """HBM bytes per pair-kernel launch from the committed --pmc summary, or
+    None when it is missing or was taken on different kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("kernel") != kernel_name:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -63,6 +102,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the steps, copy a buffer of this many bytes (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -107,6 +148,15 @@ def main(argv=None):
     kern_ms = kt["forward_ms"] / max(kt["forward_launches"], 1)
     achieved = FLOPS_PER_PAIR_Q * work / (kern_ms / 1e3) / 1e12
     bj, qc = ctx.variant()
+    kname = f"k_forward<{qc}, {bj}>"
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe)
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read and written once")
     log(f"{ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f}), pair kernel {kern_ms:.3f} ms, "
         f"{value:.4e} pair*q/s, variant bj={bj} qc={qc}")
 
@@ -126,8 +176,10 @@ def main(argv=None):
         "config": {"workload": "dna_rod_50k", "atoms": m.n, "nq": len(m.q), "q_range": [0.0, 1.0], "types": 5,
                    "pair_q_per_step": work, "variant": {"bj": bj, "qc": qc}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_forward", "kernel_ms": kern_ms, "flops_per_pair_q": FLOPS_PER_PAIR_Q},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(kname),
+                     "kernel": kname, "kernel_ms": kern_ms, "flops_per_pair_q": FLOPS_PER_PAIR_Q,
+                     "executed_fp32_tflops": EXEC_FLOPS_PER_PAIR_Q * work / (kern_ms / 1e3) / 1e12,
+                     "issue_frac": (work / (kern_ms / 1e3)) / ISSUE_CEILING_PAIR_Q},
     }
 
     # accuracy of the timed output against the stored FP64 oracle profile

@@ -5,8 +5,9 @@
 //     C = sum_m U_m cos(q_m r),  S = sum_m V_m sin(q_m r),
 //     U_m = w_m f_a(q_m) f_b(q_m),  V_m = U_m / q_m   (both 0 where q_m = 0),
 //     G = 2 (C / r^2 - S / r^3),  g_i += G (x_i - x_j),  g_j -= G (x_i - x_j).
-// The pair loop is the forward kernel's: one 64-lane wave per (I block, strip
-// of J blocks, q chunk), J blocks staged in LDS, the same FP64 set-up and the
+// The pair loop follows the forward kernel: one 64-lane wave per (I block of
+// 128 atoms, two per lane, strip of J blocks, q chunk), J blocks staged in
+// LDS, the same FP64 set-up and the
 // same FP32 recurrence z_{m+1} = z_m + d_m, d_{m+1} = d_m - lambda z_{m+1}
 // with z_m = sin(phi_m), phi_m = q_s r + m dp.  The cosine comes from the
 // recurrence state itself, cos(phi_m) = (d_m + (lambda/2) z_m) / sin(dp), so a
@@ -16,7 +17,8 @@
 // wave may hold atoms of several types; the wave visits each type present
 // (almost always one) with the other lanes masked, so that U and V are
 // wave-uniform and read from LDS.  The i-side sums stay in the lane (FP64);
-// the j-side sums are reduced over the 64 lanes per j and kept in FP64 in LDS.
+// the j-side sums (both atoms of a lane added first) are reduced over the 64
+// lanes per j with DPP row operations and kept in FP64 in LDS.
 // Partial sums go to per-strip rows that a second kernel adds in fixed order.
 #include <hip/hip_runtime.h>
 
@@ -26,10 +28,80 @@
 
 namespace sas {
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+// Sum over the 64 lanes with DPP row operations (pairs, quads, half rows,
+// rows, then the row broadcasts); the total ends in lanes 48..63 and is
+// returned from lane 63 as a wave-uniform value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int moved = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+  return v + __int_as_float(moved);
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  v = dpp_add<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xF>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);  // row_mirror
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Per-pair FP64 set-up shared by the two atoms of a lane.
+struct AdjSeed {
+  float z, d, nlam, sg;
+  double ir, omc, isdp, c0;  // 1/r, 1 - cos(dp), 1/sin(dp), cos(q_s r)
+  double dx, dy, dz;
+  bool valid;
+};
+
+__device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj, bool use, double dq, double qs) {
+  AdjSeed p;
+  p.dx = pi.x - pj.x;
+  p.dy = pi.y - pj.y;
+  p.dz = pi.z - pj.z;
+  const double r2raw = fma(p.dz, p.dz, fma(p.dy, p.dy, p.dx * p.dx));
+  p.valid = use && r2raw > 0.0;
+  const double r2 = fmax(r2raw, 1e-60);
+  p.ir = rsqrt_f64(r2);
+  const double r = r2 * p.ir;
+  const double delta = dq * r;
+  const double k = rint(delta * kOneOverPi);
+  double dp = fma(-k, kPiA, delta);
+  dp = fma(-k, kPiB, dp);
+  dp = fma(-k, kPiC, dp);
+  const SinCos hh = sincos_small(0.5 * dp);
+  const double sdp = 2.0 * hh.s * hh.c;  // sin(dp)
+  p.omc = 2.0 * hh.s * hh.s;             // 1 - cos(dp) = lambda / 2
+  // 1/sin(dp): hardware estimate and two Newton steps (0 when sin(dp) = 0)
+  double y = __builtin_amdgcn_rcp(sdp);
+  y = y * fma(-sdp, y, 2.0);
+  y = y * fma(-sdp, y, 2.0);
+  p.isdp = sdp != 0.0 ? y : 0.0;
+  double S0 = 0.0, C0 = 1.0;
+  if (qs != 0.0) {
+    const SinCos t0 = sincos_any(qs * r);
+    S0 = t0.s;
+    C0 = t0.c;
+  }
+  p.c0 = C0;
+  p.z = static_cast<float>(S0);
+  p.d = static_cast<float>(fma(C0, sdp, -S0 * p.omc));
+  p.nlam = static_cast<float>(-2.0 * p.omc);
+  p.sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
+  return p;
+}
+
+// G (x_i - x_j) of one pair from its six accumulators.
+__device__ __forceinline__ double adj_force(const AdjSeed& p, float a1e, float a1o, float a2e, float a2o, float a3e,
+                                            float a3o, double dq, float u0) {
+  const double A1 = static_cast<double>(a1e) + p.sg * static_cast<double>(a1o);
+  const double A2 = static_cast<double>(a2e) + p.sg * static_cast<double>(a2o);
+  const double A3 = static_cast<double>(a3e) + p.sg * static_cast<double>(a3o);
+  // sum_m U_m cos(q_m r); with a single q (dq = 0), or dq r an exact multiple
+  // of pi, the recurrence is constant and the seed's cosine is used
+  const double Cc = (dq != 0.0 && p.isdp != 0.0) ? (A1 + p.omc * A2) * p.isdp : static_cast<double>(u0) * p.c0;
+  return p.valid ? 2.0 * p.ir * p.ir * (Cc - A3 * p.ir) : 0.0;
 }
 
 template <int BJ>
@@ -46,11 +118,13 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   const StructDesc d = a.sd.get(0);
   const StripPos sp = decode_strip(t, d.n, a.geo);
   const int n = d.n;
-  const int i = sp.I * kWave + lane;
-  const bool vi = i < n;
-  const int ic = vi ? i : n - 1;
-  const double4 pi = a.xyz[d.atom_off + ic];
-  const int ta = clamp_type(a.tsort[d.atom_off + ic], a.T);
+  // two atoms per lane: rows I*128 + lane and I*128 + 64 + lane
+  const int i1 = sp.I * 2 * kWave + lane, i2 = i1 + kWave;
+  const bool v1 = i1 < n, v2 = i2 < n;
+  const double4 p1 = a.xyz[d.atom_off + (v1 ? i1 : n - 1)];
+  const double4 p2 = a.xyz[d.atom_off + (v2 ? i2 : n - 1)];
+  const int t1 = clamp_type(a.tsort[d.atom_off + (v1 ? i1 : n - 1)], a.T);
+  const int t2 = clamp_type(a.tsort[d.atom_off + (v2 ? i2 : n - 1)], a.T);
 
   const int m0 = blockIdx.y * a.qa;
   const int nqa = min(a.qa, a.Nq - m0);
@@ -60,7 +134,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   const int64_t pidx = static_cast<int64_t>(blockIdx.y) * a.n_strips + t;
   const int32_t* toff = a.toff;
 
-  double gx = 0.0, gy = 0.0, gz = 0.0;
+  double g1x = 0.0, g1y = 0.0, g1z = 0.0, g2x = 0.0, g2y = 0.0, g2z = 0.0;
 
 #pragma unroll 1
   for (int J = sp.Ja; J < sp.Jb; ++J) {
@@ -84,13 +158,15 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
       const int sa = static_cast<int>(max(static_cast<int64_t>(toff[tb]), aj0) - d.atom_off);
       const int sb = static_cast<int>(min(static_cast<int64_t>(toff[tb + 1]), aj1) - d.atom_off);
       if (sa >= sb) continue;
-      uint64_t remaining = __ballot(vi);
+      uint64_t rem1 = __ballot(v1), rem2 = __ballot(v2);
 #pragma unroll 1
-      while (remaining) {
-        const int src = __ffsll(static_cast<unsigned long long>(remaining)) - 1;
-        const int at = __shfl(ta, src, kWave);
-        const bool mine = vi && ta == at;
-        remaining &= ~static_cast<uint64_t>(__ballot(mine));
+      while (rem1 | rem2) {
+        // the next type present among the lanes' atoms (wave-uniform)
+        const int at = rem1 ? __shfl(t1, __ffsll(static_cast<unsigned long long>(rem1)) - 1, kWave)
+                            : __shfl(t2, __ffsll(static_cast<unsigned long long>(rem2)) - 1, kWave);
+        const bool mine1 = v1 && t1 == at, mine2 = v2 && t2 == at;
+        rem1 &= ~static_cast<uint64_t>(__ballot(mine1));
+        rem2 &= ~static_cast<uint64_t>(__ballot(mine2));
         // wave-uniform weights of the (at, tb) type pair for this chunk
         __syncthreads();
         const float* fa = a.tabp + static_cast<int64_t>(at) * a.ldt + m0;
@@ -111,31 +187,11 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
 #pragma unroll 1
         for (int jl = sa; jl < sb; ++jl) {
           const double4 pj = sj[jl - j0];
-          const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          const double r2raw = fma(dz, dz, fma(dy, dy, dx * dx));
-          const bool valid = mine && jl > i && r2raw > 0.0;
-          const double r2 = fmax(r2raw, 1e-60);
-          const double ir = rsqrt_f64(r2);
-          const double r = r2 * ir;
-          const double delta = dq * r;
-          const double k = rint(delta * kOneOverPi);
-          double dp = fma(-k, kPiA, delta);
-          dp = fma(-k, kPiB, dp);
-          dp = fma(-k, kPiC, dp);
-          const SinCos hh = sincos_small(0.5 * dp);
-          const double sdp = 2.0 * hh.s * hh.c;  // sin(dp)
-          const double omc = 2.0 * hh.s * hh.s;  // 1 - cos(dp) = lambda / 2
-          const float nlam = static_cast<float>(-2.0 * omc);
-          const float sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
-          double S0 = 0.0, C0 = 1.0;
-          if (qs != 0.0) {
-            const SinCos t0 = sincos_any(qs * r);
-            S0 = t0.s;
-            C0 = t0.c;
-          }
-          float z = static_cast<float>(S0);
-          float dd = static_cast<float>(fma(C0, sdp, -S0 * omc));
+          const AdjSeed A = adj_seed(p1, pj, mine1 && jl > i1, dq, qs);
+          const AdjSeed B = adj_seed(p2, pj, mine2 && jl > i2, dq, qs);
+          float za = A.z, da = A.d, zb = B.z, db = B.d;
           float a1e = 0.f, a1o = 0.f, a2e = 0.f, a2o = 0.f, a3e = 0.f, a3o = 0.f;
+          float b1e = 0.f, b1o = 0.f, b2e = 0.f, b2o = 0.f, b3e = 0.f, b3o = 0.f;
 #pragma unroll 1
           for (int m = 0; m < nq8; m += 8) {
             const float4 ua = ul4[m >> 2], ub = ul4[(m >> 2) + 1];
@@ -144,34 +200,41 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
             const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
 #pragma unroll
             for (int s = 0; s < 8; s += 2) {
-              a1e = fmaf(uu[s], dd, a1e);
-              a2e = fmaf(uu[s], z, a2e);
-              a3e = fmaf(vv[s], z, a3e);
-              z += dd;
-              dd = fmaf(nlam, z, dd);
-              a1o = fmaf(uu[s + 1], dd, a1o);
-              a2o = fmaf(uu[s + 1], z, a2o);
-              a3o = fmaf(vv[s + 1], z, a3o);
-              z += dd;
-              dd = fmaf(nlam, z, dd);
+              a1e = fmaf(uu[s], da, a1e);
+              b1e = fmaf(uu[s], db, b1e);
+              a2e = fmaf(uu[s], za, a2e);
+              b2e = fmaf(uu[s], zb, b2e);
+              a3e = fmaf(vv[s], za, a3e);
+              b3e = fmaf(vv[s], zb, b3e);
+              za += da;
+              zb += db;
+              da = fmaf(A.nlam, za, da);
+              db = fmaf(B.nlam, zb, db);
+              a1o = fmaf(uu[s + 1], da, a1o);
+              b1o = fmaf(uu[s + 1], db, b1o);
+              a2o = fmaf(uu[s + 1], za, a2o);
+              b2o = fmaf(uu[s + 1], zb, b2o);
+              a3o = fmaf(vv[s + 1], za, a3o);
+              b3o = fmaf(vv[s + 1], zb, b3o);
+              za += da;
+              zb += db;
+              da = fmaf(A.nlam, za, da);
+              db = fmaf(B.nlam, zb, db);
             }
           }
-          const double A1 = static_cast<double>(a1e) + sg * static_cast<double>(a1o);
-          const double A2 = static_cast<double>(a2e) + sg * static_cast<double>(a2o);
-          const double A3 = static_cast<double>(a3e) + sg * static_cast<double>(a3o);
-          // sum_m U_m cos(q_m r); with dq = 0 (a single q) the recurrence is
-          // constant and the cosine is the seed's
-          // (sdp = 0 with dq != 0 needs dq r to be an exact multiple of pi in
-          // FP64; the seed's cosine is used there too)
-          const double Cc = (dq != 0.0 && sdp != 0.0) ? (A1 + omc * A2) / sdp : static_cast<double>(u0) * C0;
-          const double G = valid ? 2.0 * ir * ir * (Cc - A3 * ir) : 0.0;
-          const double cx = G * dx, cy = G * dy, cz = G * dz;
-          gx += cx;
-          gy += cy;
-          gz += cz;
-          const float sx = wave_sum(static_cast<float>(cx));
-          const float sy = wave_sum(static_cast<float>(cy));
-          const float sz = wave_sum(static_cast<float>(cz));
+          const double GA = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, u0);
+          const double GB = adj_force(B, b1e, b1o, b2e, b2o, b3e, b3o, dq, u0);
+          const double cax = GA * A.dx, cay = GA * A.dy, caz = GA * A.dz;
+          const double cbx = GB * B.dx, cby = GB * B.dy, cbz = GB * B.dz;
+          g1x += cax;
+          g1y += cay;
+          g1z += caz;
+          g2x += cbx;
+          g2y += cby;
+          g2z += cbz;
+          const float sx = wave_total(static_cast<float>(cax + cbx));
+          const float sy = wave_total(static_cast<float>(cay + cby));
+          const float sz = wave_total(static_cast<float>(caz + cbz));
           if (lane == 0) {
             double* gj = gjl + 3 * (jl - j0);
             gj[0] -= sx;
@@ -185,10 +248,13 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
     double* outj = a.gJ + (pidx * a.geo.g * BJ + static_cast<int64_t>(J - sp.Ja) * BJ) * 3;
     for (int k = lane; k < 3 * (j1 - j0); k += kWave) outj[k] = gjl[k];
   }
-  double* outi = a.gI + (pidx * kWave + lane) * 3;
-  outi[0] = gx;
-  outi[1] = gy;
-  outi[2] = gz;
+  double* outi = a.gI + pidx * (2 * kWave) * 3;
+  outi[3 * lane + 0] = g1x;
+  outi[3 * lane + 1] = g1y;
+  outi[3 * lane + 2] = g1z;
+  outi[3 * (lane + kWave) + 0] = g2x;
+  outi[3 * (lane + kWave) + 1] = g2y;
+  outi[3 * (lane + kWave) + 2] = g2z;
 }
 
 // One thread per (sorted) atom: the i-side rows of its own row of strips and
@@ -199,9 +265,9 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
   const StructDesc d = a.sd.get(0);
   const int64_t at = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (at >= d.n) return;
-  const int64_t n = d.n, c = a.geo.c, g = a.geo.g, bj = a.geo.bj;
-  const int64_t nI = ceil_div(n, kWave), nJ = ceil_div(n, bj);
-  const int64_t I = at / kWave, lane = at % kWave, J = at / bj;
+  const int64_t n = d.n, c = a.geo.c, g = a.geo.g, bj = a.geo.bj, ib = a.geo.ib;
+  const int64_t nI = ceil_div(n, ib), nJ = ceil_div(n, bj);
+  const int64_t I = at / ib, lane = at % ib, J = at / bj;
   double sx = 0.0, sy = 0.0, sz = 0.0;
   if (n >= 2) {
     for (int32_t ch = 0; ch < nchunks; ++ch) {
@@ -209,7 +275,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
       const int64_t first = row_first_strip(I, nJ, c, g);
       const int64_t spr = ceil_div(nJ - I / c, g);
       for (int64_t s = first; s < first + spr; ++s) {
-        const double* p = a.gI + ((base + s) * kWave + lane) * 3;
+        const double* p = a.gI + ((base + s) * ib + lane) * 3;
         sx += p[0];
         sy += p[1];
         sz += p[2];
@@ -233,13 +299,12 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
   grad_out[dst * 3 + 2] = sz;
 }
 
-bool adjoint_bj_supported(int32_t bj) { return bj == 64 || bj == 128 || bj == 256; }
+bool adjoint_bj_supported(int32_t bj) { return bj == 128 || bj == 256; }
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st) {
   if (a.n_strips <= 0) return hipSuccess;
   const dim3 grid(static_cast<uint32_t>(a.n_strips), nchunks);
   switch (a.geo.bj) {
-    case 64: hipLaunchKernelGGL((k_adjoint<64>), grid, dim3(kWave), 0, st, a); break;
     case 128: hipLaunchKernelGGL((k_adjoint<128>), grid, dim3(kWave), 0, st, a); break;
     case 256: hipLaunchKernelGGL((k_adjoint<256>), grid, dim3(kWave), 0, st, a); break;
     default: return hipErrorInvalidValue;

@@ -174,6 +174,7 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   sc.ldt = (sc.nchunks - 1) * qc + sc.qc_template;
   int32_t bj = bj_override > 0 ? bj_override : (ctx && ctx->force_bj > 0 ? ctx->force_bj : default_bj(max_n));
   sc.geo.bj = bj;
+  sc.geo.ib = sas::kWave;
   sc.geo.c = bj / sas::kWave;
   // strips of g J blocks: g = 1 unless the partial rows would exceed 256 MiB
   for (int32_t g = 1;; g *= 2) {
@@ -247,7 +248,8 @@ std::string workload_key(const std::vector<int64_t>& sizes, int32_t T, int32_t N
 void add_adjoint(Schedule* sc, int64_t n, int32_t Nq) {
   sc->grad = true;
   sc->geo_adj.bj = 128;
-  sc->geo_adj.c = 128 / sas::kWave;
+  sc->geo_adj.ib = 2 * sas::kWave;
+  sc->geo_adj.c = 1;
   sc->geo_adj.g = 1;
   sc->n_strips_adj = sas::strips_of(n, sc->geo_adj);
   const int32_t nch = (Nq + sas::kAdjQ - 1) / sas::kAdjQ;
@@ -276,7 +278,7 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   L.slices = take(sizeof(double) * sc.n_slices * Nq);
   if (sc.grad) {
     const size_t rows = static_cast<size_t>(sc.nchunks_adj) * sc.n_strips_adj;
-    L.gI = take(sizeof(double) * 3 * rows * sas::kWave);
+    L.gI = take(sizeof(double) * 3 * rows * sc.geo_adj.ib);
     L.gJ = take(sizeof(double) * 3 * rows * sc.geo_adj.g * sc.geo_adj.bj);
   }
   L.total = p;

@@ -32,12 +32,13 @@ struct DescView {
   __device__ __forceinline__ StructDesc get(int s) const { return S == 1 ? one : arr[s]; }
 };
 
-// Tile geometry for one launch: I blocks of kWave atoms, J blocks of bj atoms,
+// Tile geometry for one launch: I blocks of ib atoms, J blocks of bj atoms,
 // strips of up to g J blocks.
 struct Geometry {
-  int32_t bj;  // atoms per J block (multiple of kWave)
-  int32_t c;   // bj / kWave
+  int32_t bj;  // atoms per J block (multiple of ib)
+  int32_t c;   // bj / ib
   int32_t g;   // J blocks per strip
+  int32_t ib;  // atoms per I block (64 forward: one per lane; 128 adjoint: two per lane)
 };
 
 struct ForwardArgs {
@@ -67,7 +68,7 @@ struct AdjArgs {
   int32_t T, Nq;
   int32_t qa;           // q values per chunk (<= kAdjQ); grid.y = chunks
   const double* w;      // dL/dI [Nq]
-  double* gI;           // [chunks][strips][64][3] i-side partial sums
+  double* gI;           // [chunks][strips][ib][3] i-side partial sums
   double* gJ;           // [chunks][strips][g*bj][3] j-side partial sums
   int64_t n_strips;
   double q0, dq;

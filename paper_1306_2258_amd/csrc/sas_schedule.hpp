@@ -8,7 +8,7 @@
 namespace sas {
 
 // ---------------------------------------------------------------------------
-// Strip bookkeeping.  I blocks hold kWave atoms, J blocks bj = c*kWave atoms,
+// Strip bookkeeping.  I blocks hold ib atoms, J blocks bj = c*ib atoms,
 // both in the type-sorted order of one structure.  Row I needs J blocks
 // J >= floor(I/c) (earlier blocks hold only j < i).  Rows are grouped into
 // "super-rows" u = floor(I/c) of c rows with nJ-u J blocks each, cut into
@@ -38,7 +38,7 @@ struct StripPos {
 };
 
 __device__ inline StripPos decode_strip(int64_t t, int32_t n, const Geometry& geo) {
-  const int64_t nI = ceil_div(n, kWave), nJ = ceil_div(n, geo.bj), c = geo.c, g = geo.g;
+  const int64_t nI = ceil_div(n, geo.ib), nJ = ceil_div(n, geo.bj), c = geo.c, g = geo.g;
   const int64_t nsup = ceil_div(nI, c);
   // largest u in [0, nsup) with strips_before(u) <= t
   int64_t lo = 0, hi = nsup - 1;

@@ -72,7 +72,7 @@ def check(sd, m, w, tol=GTOL, atoms=None):
     return g
 
 
-@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 129, 300, 1000])
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 127, 128, 129, 255, 257, 300, 1000])
 def test_grad_sizes(sd, n):
     say(f"grad N={n}")
     m = W.random_molecule(2000 + n, n, 24, q0=0.0, q1=0.9, extent=3.0 * n ** (1 / 3) + 2.0)
