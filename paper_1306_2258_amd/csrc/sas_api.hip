@@ -138,10 +138,13 @@ int32_t pick_qc_template(int32_t qc) {
   return 200;
 }
 
+// J-block size by the largest structure (measured on MI355X: 512 atoms for
+// the 50,000-atom rod, 256 for 20,000 atoms, 128 for 10,000): long enough to
+// amortise the per-segment lane reduction, short enough to leave many strips.
 int32_t default_bj(int64_t max_n) {
-  if (max_n >= 16384) return 512;
-  if (max_n >= 2048) return 256;
-  if (max_n >= 512) return 128;
+  if (max_n >= 40000) return 512;
+  if (max_n >= 15000) return 256;
+  if (max_n >= 2048) return 128;
   return 64;
 }
 
@@ -214,21 +217,17 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   return sc;
 }
 
-// Tile shapes a plan may time: every J-block size, with the default q chunk
-// and (where a smaller template exists) half of it.  A forced variant is the
-// only candidate.
+// Tile shapes a plan may time: every J-block size with the default q chunk
+// (halving the chunk was always slower on MI355X: each chunk repeats the
+// per-pair FP64 set-up).  A forced variant is the only candidate.
 std::vector<std::pair<int32_t, int32_t>> tile_candidates(const sas_ctx* ctx, int32_t Nq) {
+  (void)Nq;
   std::vector<std::pair<int32_t, int32_t>> out;
   if (ctx && (ctx->force_bj > 0 || ctx->force_qc > 0)) {
     out.emplace_back(ctx->force_bj, ctx->force_qc);
     return out;
   }
-  const int32_t nch = (Nq + 199) / 200;
-  const int32_t qdef = pick_qc_template((Nq + nch - 1) / nch);
-  std::vector<int32_t> qcs{qdef};
-  if (qdef >= 100 && Nq > 50) qcs.push_back(qdef / 2);
-  for (int32_t bj : {64, 128, 256, 512})
-    for (int32_t qc : qcs) out.emplace_back(bj, qc == qdef ? 0 : qc);
+  for (int32_t bj : {64, 128, 256, 512}) out.emplace_back(bj, 0);
   return out;
 }
 
