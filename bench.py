@@ -106,7 +106,7 @@ def main(argv=None):
                     help="after the steps, copy a buffer of this many bytes (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
 
     import torch
