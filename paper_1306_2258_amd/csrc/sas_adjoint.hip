@@ -71,8 +71,10 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   dp = fma(-k, kPiB, dp);
   dp = fma(-k, kPiC, dp);
   const SinCos hh = sincos_small(0.5 * dp);
-  const double sdp = 2.0 * hh.s * hh.c;  // sin(dp)
-  p.omc = 2.0 * hh.s * hh.s;             // 1 - cos(dp) = lambda / 2
+  const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
+  const double lam = s2 * s2;     // 4 sin^2(dp/2)
+  const double sdp = s2 * hh.c;   // sin(dp)
+  p.omc = 0.5 * lam;              // 1 - cos(dp) = lambda / 2
   // 1/sin(dp): hardware estimate and two Newton steps (0 when sin(dp) = 0)
   double y = __builtin_amdgcn_rcp(sdp);
   y = y * fma(-sdp, y, 2.0);
@@ -87,8 +89,8 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   p.c0 = C0;
   p.z = static_cast<float>(S0);
   p.d = static_cast<float>(fma(C0, sdp, -S0 * p.omc));
-  p.nlam = static_cast<float>(-2.0 * p.omc);
-  p.sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
+  p.nlam = static_cast<float>(-lam);
+  p.sg = parity_sign(k);
   return p;
 }
 

@@ -181,20 +181,23 @@ __device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& 
   dp = fma(-k, kPiB, dp);
   dp = fma(-k, kPiC, dp);
   const SinCos hh = sincos_small(0.5 * dp);
-  const double sdp = 2.0 * hh.s * hh.c;  // sin(dp)
-  const double omc = 2.0 * hh.s * hh.s;  // 1 - cos(dp) = lambda / 2
-  const double w = use ? ir : 0.0;
-  double S0 = 0.0, C0 = w;
-  if (qs != 0.0) {
-    const SinCos t0 = sincos_any(qs * r);
-    S0 = t0.s * w;
-    C0 = t0.c * w;
-  }
+  const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
+  const double lam = s2 * s2;     // 4 sin^2(dp/2) = 2 (1 - cos(dp))
+  const double sdp = s2 * hh.c;   // sin(dp)
   PairSeed p;
-  p.z = static_cast<float>(S0);
-  p.d = static_cast<float>(fma(C0, sdp, -S0 * omc));
-  p.nlam = static_cast<float>(-2.0 * omc);
-  p.sg = (static_cast<int>(k) & 1) ? -1.f : 1.f;
+  p.nlam = static_cast<float>(-lam);
+  p.sg = parity_sign(k);
+  if (qs == 0.0) {
+    // chunk starting at q = 0: z_0 = 0, d_0 = sin(dp)/r
+    p.z = 0.f;
+    p.d = use ? static_cast<float>(sdp * ir) : 0.f;
+  } else {
+    const SinCos t0 = sincos_any(qs * r);
+    const double w = use ? ir : 0.0;
+    const double S0 = t0.s * w, C0 = t0.c * w;
+    p.z = static_cast<float>(S0);
+    p.d = static_cast<float>(fma(C0, sdp, -0.5 * lam * S0));
+  }
   return p;
 }
 
@@ -232,7 +235,7 @@ __device__ __forceinline__ float lane_allreduce_tail(float* acc, int lane) {
 }
 
 template <int QC, int BJ>
-__global__ __launch_bounds__(kWave, 2) void k_forward(ForwardArgs a) {
+__global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs a) {
   constexpr int NG = QC / kWave;          // full groups of 64 q values
   constexpr int R = QC % kWave;           // values in the tail group
   constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
