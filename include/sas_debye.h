@@ -24,9 +24,13 @@
  *    stream reaches the call.  No call synchronises the stream.
  *  - Scratch memory is the caller's `workspace` (dev, 256-byte aligned) of at
  *    least the size the matching *_workspace_size query returns.
- *  - The q grid must be uniform: q_m = q_0 + m dq within 8 ulp of max q,
- *    q_0 >= 0, strictly increasing, all finite (Results section: profiles on
- *    uniformly spaced q).  Nq = 1 is always accepted.
+ *  - The q grid is host double [nq], finite, q_0 >= 0 and strictly
+ *    increasing.  A uniform grid (q_m = q_0 + m dq within 8 ulp of max q; the
+ *    Results section evaluates profiles on such grids; Nq <= 2 always counts
+ *    as uniform) takes the fast path: the pair kernel steps sin(q r) from one
+ *    q to the next by a recurrence.  Any other grid is evaluated directly,
+ *    one sine per pair and q, at a few times the cost per pair and q.  The
+ *    profile calls accept both; sas_debye_grad needs a uniform grid.
  *  - Results are FP64.  Pair terms are evaluated in FP32 from FP64 per-pair
  *    set-up values; every cross-lane and cross-block sum beyond one 64-lane
  *    wave is FP64 and in a fixed order, so two identical calls give bitwise
@@ -54,7 +58,7 @@ extern "C" {
 typedef enum {
   SAS_OK = 0,
   SAS_ERR_INVALID_ARG = 1,         /* null pointer, negative size, bad offsets, ...       */
-  SAS_ERR_Q_NOT_UNIFORM = 2,       /* q is not finite / non-negative / increasing / uniform */
+  SAS_ERR_Q_NOT_UNIFORM = 2,       /* q not finite / non-negative / increasing (uniform where required) */
   SAS_ERR_UNSUPPORTED = 3,         /* a size beyond the documented limits                  */
   SAS_ERR_WORKSPACE_TOO_SMALL = 4, /* ws_bytes below the size the query returns            */
   SAS_ERR_OUT_OF_MEMORY = 5,       /* a host or device allocation of the library failed   */
@@ -88,8 +92,9 @@ const char* sas_status_string(sas_status s);
  * > SAS_MAX_NQ), SAS_ERR_Q_NOT_UNIFORM. */
 sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq);
 
-/* Workspace bytes needed by sas_debye_profile (grad = 0) or sas_debye_grad
- * (grad = 1) for these sizes.  Returns 0 for invalid sizes. */
+/* Workspace bytes needed by sas_debye_profile (grad = 0; enough for a
+ * uniform or a non-uniform grid) or sas_debye_grad (grad = 1) for these
+ * sizes.  Returns 0 for invalid sizes. */
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad);
 
 /*
@@ -99,7 +104,7 @@ size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_
  *   n                             number of atoms, 0 <= n <= SAS_MAX_ATOMS
  *   table   dev  float [t][nq]    f_type(q_m), row-major
  *   t                             number of types, 1 <= t <= SAS_MAX_TYPES
- *   q       host double [nq]      uniform grid (see conventions)
+ *   q       host double [nq]      q grid, uniform or not (see conventions)
  *   nq                            1 <= nq <= SAS_MAX_NQ
  *   I_out   dev  double [nq]      written: I(q_m)
  *   workspace/ws_bytes            dev scratch, >= sas_debye_workspace_size(ctx,n,t,nq,0)
@@ -151,6 +156,7 @@ void sas_plan_destroy(sas_plan* plan);
  *   dL_dI    dev double [nq]    weights (e.g. dchi2/dI)
  *   grad_out dev double [n][3]  written, in the caller's atom order
  *   I_out    dev double [nq] or NULL: if given, the profile is written too
+ * q must be a uniform grid (SAS_ERR_Q_NOT_UNIFORM otherwise).
  * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 1).
  */
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
@@ -161,7 +167,8 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
  * Tuning controls (optional).  sas_set_variant forces the forward tile shape
  * for subsequent calls on ctx: bj = atoms per J block (64, 128, 256 or 512;
  * 0 = automatic) and qc = q values per chunk (one of 16, 32, 64, 100, 128,
- * 200; 0 = automatic).  Returns SAS_ERR_INVALID_ARG for other values.
+ * 200; 0 = automatic; a non-uniform grid always uses chunks of at most 32).
+ * Returns SAS_ERR_INVALID_ARG for other values.
  * sas_get_variant reports the shape the last forward call used.
  */
 sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc);

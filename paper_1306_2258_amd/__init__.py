@@ -15,7 +15,9 @@ Tensor conventions
 coords  float32 [N, 3] on the GPU (Angstrom)
 types   int32   [N]    on the GPU, values in [0, T)
 table   float32 [T, Nq] on the GPU: f_type(q_m)
-q       1-D float64 host array / list / CPU tensor (1/Angstrom), uniform
+q       1-D float64 host array / list / CPU tensor (1/Angstrom): finite,
+        >= 0, strictly increasing; uniform grids take the recurrence path,
+        other grids are evaluated directly (the gradient needs uniform q)
 results float64 on the GPU
 """
 from __future__ import annotations
@@ -153,7 +155,7 @@ def _check_inputs(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor
 
 def debye_profile(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, *,
                   ctx: Optional[Context] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """I(q_m) for every q_m of a uniform grid (float64 [Nq] on the GPU)."""
+    """I(q_m) for every q_m of the grid (float64 [Nq] on the GPU)."""
     _check_inputs(coords, types, table)
     ctx = ctx or default_context(coords.device)
     qh = _q_host(q)
@@ -244,7 +246,7 @@ class BatchedPlan:
 def debye_grad(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, dL_dI: torch.Tensor, *,
                with_profile: bool = False, ctx: Optional[Context] = None):
     """sum_m dL_dI[m] dI(q_m)/dcoords as float64 [N, 3] (and the profile if
-    ``with_profile``)."""
+    ``with_profile``); q must be a uniform grid."""
     _check_inputs(coords, types, table)
     ctx = ctx or default_context(coords.device)
     qh = _q_host(q)

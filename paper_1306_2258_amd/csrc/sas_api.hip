@@ -114,6 +114,7 @@ struct DeviceGuard {
 
 struct Schedule {
   Geometry geo{};
+  bool direct = false;  // arbitrary q grid: per-q evaluation instead of the recurrence
   int32_t qc = 0, qc_template = 0;
   int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
   // adjoint (gradient) schedule, single structure only
@@ -128,8 +129,19 @@ struct Schedule {
 };
 
 struct Layout {
-  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, desc = 0, tabp = 0, partial = 0, slices = 0;
+  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, tabp = 0, partial = 0, slices = 0;
   size_t gI = 0, gJ = 0, total = 0;
+  // host-written block, uploaded in one copy: structure descriptors (S > 1)
+  // followed by the q grid (direct form)
+  size_t upload = 0, upload_bytes = 0, desc = 0, qdev = 0;
+};
+
+// A validated q grid: finite, >= 0, strictly increasing; uniform or not.
+struct QGrid {
+  const double* host = nullptr;
+  int32_t nq = 0;
+  double q0 = 0.0, dq = 0.0;
+  bool uniform = false;
 };
 
 int32_t pick_qc_template(int32_t qc) {
@@ -150,8 +162,9 @@ int32_t default_bj(int64_t max_n) {
 
 // Build the schedule for structure sizes `sizes` (caller order).
 Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
-                       int32_t bj_override = 0, int32_t qc_override = 0) {
+                       int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false) {
   Schedule sc;
+  sc.direct = direct;
   sc.S = static_cast<int32_t>(sizes.size());
   int64_t max_n = 0;
   for (int64_t n : sizes) {
@@ -160,7 +173,12 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   }
   // q chunking: one chunk up to 200 values, else balanced chunks of <= 200
   int32_t qc = Nq;
-  if (qc_override > 0) {
+  if (direct) {
+    // per-q evaluation: balanced chunks of at most 32 q values
+    const int32_t nch = (Nq + 31) / 32;
+    qc = (Nq + nch - 1) / nch;
+    sc.qc_template = 32;
+  } else if (qc_override > 0) {
     const int32_t nch = (Nq + qc_override - 1) / qc_override;
     qc = (Nq + nch - 1) / nch;
     sc.qc_template = pick_qc_template(qc);
@@ -271,7 +289,14 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   L.perm = take(sizeof(int32_t) * sc.n_total);
   L.bcount = take(sizeof(int32_t) * sc.n_pack * T);
   L.toff = take(sizeof(int32_t) * static_cast<size_t>(sc.S) * (T + 1));
-  L.desc = take(sc.S > 1 ? sizeof(StructDesc) * sc.S : 0);
+  {
+    const size_t dbytes = sc.S > 1 ? align_up(sizeof(StructDesc) * sc.S) : 0;
+    const size_t qbytes = sc.direct ? sizeof(double) * static_cast<size_t>(Nq) : 0;
+    L.upload_bytes = dbytes + qbytes;
+    L.upload = take(L.upload_bytes);
+    L.desc = L.upload;
+    L.qdev = L.upload + dbytes;
+  }
   L.tabp = take(sizeof(float) * static_cast<size_t>(T) * sc.ldt);
   L.partial = take(sizeof(double) * sc.n_strips * Nq);
   L.slices = take(sizeof(double) * sc.n_slices * Nq);
@@ -317,11 +342,63 @@ DescView view_of(const Schedule& sc, const void* ws, const Layout& L) {
   return v;
 }
 
-// Enqueue pack -> forward -> reduce for a prepared schedule.  Descriptors must
-// already be in the workspace when S > 1.
+sas_status classify_q(const double* q, int32_t nq, QGrid* g) {
+  if (!q) return fail(SAS_ERR_INVALID_ARG, "q is NULL");
+  if (nq <= 0 || nq > SAS_MAX_NQ) return fail(SAS_ERR_INVALID_ARG, "q count %d outside [1, %d]", nq, SAS_MAX_NQ);
+  for (int32_t m = 0; m < nq; ++m) {
+    if (!std::isfinite(q[m])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] is not finite", m);
+    if (q[m] < 0.0) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] = %g is negative", m, q[m]);
+    if (m > 0 && !(q[m] > q[m - 1])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q is not strictly increasing at %d", m);
+  }
+  g->host = q;
+  g->nq = nq;
+  g->q0 = q[0];
+  g->dq = nq > 1 ? (q[nq - 1] - q[0]) / (nq - 1) : 0.0;
+  const double tol = 8.0 * (std::nextafter(q[nq - 1], INFINITY) - q[nq - 1]);
+  g->uniform = true;
+  for (int32_t m = 1; m + 1 < nq && g->uniform; ++m)
+    if (std::fabs(q[m] - (g->q0 + m * g->dq)) > tol) g->uniform = false;
+  return SAS_OK;
+}
+
+// The bytes of the upload block (descriptors, then the q grid) as the
+// device expects them.
+std::vector<char> upload_image(const Schedule& sc, const Layout& L, const QGrid& g) {
+  std::vector<char> img(L.upload_bytes, 0);
+  if (sc.S > 1) std::memcpy(img.data() + (L.desc - L.upload), sc.desc.data(), sizeof(StructDesc) * sc.S);
+  if (sc.direct) std::memcpy(img.data() + (L.qdev - L.upload), g.host, sizeof(double) * g.nq);
+  return img;
+}
+
+// Asynchronous upload through the context's pinned staging buffer.  The
+// buffer is reused once the previous upload from it has completed.
+sas_status stage_upload(sas_ctx* ctx, void* ws, const Layout& L, const std::vector<char>& img, hipStream_t hs) {
+  if (img.empty()) return SAS_OK;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (ctx->pinned_used) SAS_HIP(hipEventSynchronize(ctx->pinned_ev));
+  if (ctx->pinned_bytes < img.size()) {
+    if (ctx->pinned) SAS_HIP(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    if (hipHostMalloc(&ctx->pinned, img.size(), hipHostMallocDefault) != hipSuccess)
+      return fail(SAS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes failed", img.size());
+    ctx->pinned_bytes = img.size();
+  }
+  if (!ctx->pinned_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
+  std::memcpy(ctx->pinned, img.data(), img.size());
+  SAS_HIP(hipMemcpyAsync(static_cast<char*>(ws) + L.upload, ctx->pinned, img.size(), hipMemcpyHostToDevice, hs));
+  SAS_HIP(hipEventRecord(ctx->pinned_ev, hs));
+  ctx->pinned_used = true;
+  return SAS_OK;
+}
+
+// Enqueue pack -> forward -> reduce for a prepared schedule.  The upload
+// block (descriptors when S > 1, the q grid in the direct form) must already
+// be in the workspace.
 sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, const float* coords,
                            const int32_t* types, const float* table, int32_t T, int32_t Nq, double q0, double dq,
                            double* I_out, void* ws, hipStream_t st) {
+  const double* qdev = sc.direct ? reinterpret_cast<const double*>(static_cast<const char*>(ws) + L.qdev) : nullptr;
   char* w = static_cast<char*>(ws);
   DescView sd = view_of(sc, ws, L);
   auto* xyz = reinterpret_cast<double4*>(w + L.xyz);
@@ -349,11 +426,12 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   a.qc = sc.qc;
   a.q0 = q0;
   a.dq = dq;
+  a.qdev = qdev;
   {
     LaunchTimer timer(ctx, st, false);
     SAS_HIP(sas::launch_forward(a, sc.n_strips, sc.qc_template, st));
   }
-  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, toff, table, T, Nq, q0, dq, I_out, st));
+  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, toff, table, T, Nq, q0, dq, qdev, I_out, st));
   return SAS_OK;
 }
 
@@ -379,22 +457,12 @@ const char* sas_status_string(sas_status s) {
 }
 
 sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq) {
-  if (!q) return fail(SAS_ERR_INVALID_ARG, "q is NULL");
-  if (nq <= 0 || nq > SAS_MAX_NQ) return fail(SAS_ERR_INVALID_ARG, "q count %d outside [1, %d]", nq, SAS_MAX_NQ);
-  for (int32_t m = 0; m < nq; ++m) {
-    if (!std::isfinite(q[m])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] is not finite", m);
-    if (q[m] < 0.0) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] = %g is negative", m, q[m]);
-    if (m > 0 && !(q[m] > q[m - 1])) return fail(SAS_ERR_Q_NOT_UNIFORM, "q is not strictly increasing at %d", m);
-  }
-  const double a = q[0];
-  const double d = nq > 1 ? (q[nq - 1] - q[0]) / (nq - 1) : 0.0;
-  const double tol = 8.0 * (std::nextafter(q[nq - 1], INFINITY) - q[nq - 1]);
-  for (int32_t m = 1; m + 1 < nq; ++m) {
-    const double dev = std::fabs(q[m] - (a + m * d));
-    if (dev > tol) return fail(SAS_ERR_Q_NOT_UNIFORM, "q[%d] deviates from a uniform grid by %g", m, dev);
-  }
-  if (q0) *q0 = a;
-  if (dq) *dq = d;
+  QGrid g;
+  const sas_status st = classify_q(q, nq, &g);
+  if (st != SAS_OK) return st;
+  if (!g.uniform) return fail(SAS_ERR_Q_NOT_UNIFORM, "q is not a uniform grid");
+  if (q0) *q0 = g.q0;
+  if (dq) *dq = g.dq;
   return SAS_OK;
 }
 
@@ -492,9 +560,14 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
   if (check_sizes(n, t, nq) != SAS_OK) return 0;
-  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
-  if (grad) add_adjoint(&sc, n, nq);
-  return make_layout(sc, t, nq).total;
+  const std::vector<int64_t> sizes{n};
+  Schedule sc = make_schedule(ctx, sizes, t, nq);
+  if (grad) {
+    add_adjoint(&sc, n, nq);  // the gradient needs a uniform grid
+    return make_layout(sc, t, nq).total;
+  }
+  // the grid is not known here: cover both the uniform and the direct form
+  return std::max(make_layout(sc, t, nq).total, make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, true), t, nq).total);
 }
 
 sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
@@ -505,10 +578,10 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
   if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
-  double q0 = 0, dq = 0;
-  st = sas_q_grid_check(q, nq, &q0, &dq);
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -516,8 +589,10 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
     return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
-  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace,
-                       static_cast<hipStream_t>(stream));
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
+  if (st != SAS_OK) return st;
+  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
   if (st == SAS_OK) {
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
@@ -530,10 +605,12 @@ size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offse
   std::vector<int64_t> sizes;
   if (check_offsets(offsets, S, &sizes) != SAS_OK) return 0;
   if (check_sizes(0, t, nq) != SAS_OK) return 0;
-  // large enough for the automatic shape and for every shape a plan may time
+  // large enough for the automatic shape, every shape a plan may time, and
+  // the direct form (the grid is not known here)
   size_t need = make_layout(make_schedule(ctx, sizes, t, nq), t, nq).total;
   for (const auto& c : tile_candidates(ctx, nq))
-    need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second), t, nq).total);
+    for (bool direct : {false, true})
+      need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second, direct), t, nq).total);
   return need;
 }
 
@@ -549,11 +626,11 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   if (st != SAS_OK) return st;
   if (offsets[S] > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
   if (!table || (S > 0 && !I_out)) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
-  double q0 = 0, dq = 0;
-  st = sas_q_grid_check(q, nq, &q0, &dq);
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   if (S == 0) return SAS_OK;
-  const Schedule sc = make_schedule(ctx, sizes, t, nq);
+  const Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -562,25 +639,9 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  if (sc.S > 1) {
-    const size_t bytes = sizeof(StructDesc) * sc.S;
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    if (ctx->pinned_used) SAS_HIP(hipEventSynchronize(ctx->pinned_ev));
-    if (ctx->pinned_bytes < bytes) {
-      if (ctx->pinned) SAS_HIP(hipHostFree(ctx->pinned));
-      ctx->pinned = nullptr;
-      ctx->pinned_bytes = 0;
-      if (hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault) != hipSuccess)
-        return fail(SAS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes failed", bytes);
-      ctx->pinned_bytes = bytes;
-    }
-    if (!ctx->pinned_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
-    std::memcpy(ctx->pinned, sc.desc.data(), bytes);
-    SAS_HIP(hipMemcpyAsync(static_cast<char*>(workspace) + L.desc, ctx->pinned, bytes, hipMemcpyHostToDevice, hs));
-    SAS_HIP(hipEventRecord(ctx->pinned_ev, hs));
-    ctx->pinned_used = true;
-  }
-  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace, hs);
+  st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
+  if (st != SAS_OK) return st;
+  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
   if (st == SAS_OK) {
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
@@ -600,7 +661,8 @@ struct sas_plan {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   int32_t T = 0, Nq = 0;
-  double q0 = 0, dq = 0;
+  std::vector<double> qh;  // the plan's own copy of the q grid
+  QGrid grid;
   Schedule sc;
   Layout L;
   hipStream_t cap = nullptr;
@@ -611,10 +673,12 @@ struct sas_plan {
 
 namespace {
 
-sas_status upload_desc(const Schedule& sc, const Layout& L, void* ws) {
-  if (sc.S > 1)
-    SAS_HIP(hipMemcpy(static_cast<char*>(ws) + L.desc, sc.desc.data(), sizeof(StructDesc) * sc.S,
-                      hipMemcpyHostToDevice));
+// Synchronous upload of the host-written block (the plan's graph reads it
+// from the workspace on every replay).
+sas_status upload_sync(const Schedule& sc, const Layout& L, const QGrid& g, void* ws) {
+  const std::vector<char> img = upload_image(sc, L, g);
+  if (!img.empty())
+    SAS_HIP(hipMemcpy(static_cast<char*>(ws) + L.upload, img.data(), img.size(), hipMemcpyHostToDevice));
   return SAS_OK;
 }
 
@@ -628,17 +692,17 @@ sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
   SAS_HIP(hipEventCreate(&e1));
   sas_status status = SAS_OK;
   for (const auto& c : cands) {
-    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second);
+    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, !p->grid.uniform);
     const Layout L = make_layout(sc, p->T, p->Nq);
     if (L.total > p->ws_bytes) continue;
-    status = upload_desc(sc, L, p->ws);
+    status = upload_sync(sc, L, p->grid, p->ws);
     if (status != SAS_OK) break;
-    status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+    status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->grid.q0, p->grid.dq, p->I_out,
                              p->ws, st);
     if (status != SAS_OK) break;
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 2 && status == SAS_OK; ++r)
-      status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+      status = enqueue_forward(nullptr, sc, L, p->coords, p->types, p->table, p->T, p->Nq, p->grid.q0, p->grid.dq, p->I_out,
                                p->ws, st);
     (void)hipEventRecord(e1, st);
     if (status != SAS_OK) break;
@@ -679,12 +743,12 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   if (S == 0) return fail(SAS_ERR_INVALID_ARG, "a plan needs at least one structure");
   if (offsets[S] > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
   if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
-  double q0 = 0, dq = 0;
-  st = sas_q_grid_check(q, nq, &q0, &dq);
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  const Schedule sc0 = make_schedule(ctx, sizes, t, nq);
+  const Schedule sc0 = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform);
   const size_t need = make_layout(sc0, t, nq).total;
   if (ws_bytes < need) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, need);
   sas_plan* p = new (std::nothrow) sas_plan();
@@ -699,8 +763,9 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   p->ws_bytes = ws_bytes;
   p->T = t;
   p->Nq = nq;
-  p->q0 = q0;
-  p->dq = dq;
+  p->qh.assign(q, q + nq);
+  p->grid = grid;
+  p->grid.host = p->qh.data();
   *out = p;
   return SAS_OK;
 }
@@ -713,7 +778,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
   if (!p->ready) {
     // choose the tile shape: forced variant, cached choice, or timing
     int32_t bj = 0, qc = 0;
-    const std::string key = workload_key(p->sizes, p->T, p->Nq);
+    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->grid.uniform ? "u" : "d");
     const bool forced = p->ctx->force_bj > 0 || p->ctx->force_qc > 0;
     auto it = p->ctx->tuned.find(key);
     if (forced) {
@@ -726,16 +791,16 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
       if (st != SAS_OK) return st;
       p->ctx->tuned[key] = {bj, qc};
     }
-    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc);
+    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, !p->grid.uniform);
     p->L = make_layout(p->sc, p->T, p->Nq);
     if (p->L.total > p->ws_bytes)
       return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", p->ws_bytes, p->L.total);
-    sas_status st = upload_desc(p->sc, p->L, p->ws);
+    sas_status st = upload_sync(p->sc, p->L, p->grid, p->ws);
     if (st != SAS_OK) return st;
     // capture pack -> pair kernel -> reduce on a private stream
     if (!p->cap) SAS_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
     SAS_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
-    st = enqueue_forward(nullptr, p->sc, p->L, p->coords, p->types, p->table, p->T, p->Nq, p->q0, p->dq, p->I_out,
+    st = enqueue_forward(nullptr, p->sc, p->L, p->coords, p->types, p->table, p->T, p->Nq, p->grid.q0, p->grid.dq, p->I_out,
                          p->ws, p->cap);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(p->cap, &graph);

@@ -36,6 +36,7 @@ struct SinCos {
 // truncation adds no measurable bias.
 constexpr double kS3 = -1.0 / fact(3), kS5 = 1.0 / fact(5), kS7 = -1.0 / fact(7), kS9 = 1.0 / fact(9);
 constexpr double kS11 = -1.0 / fact(11);
+constexpr double kS13 = 1.0 / fact(13), kS15 = -1.0 / fact(15), kS17 = 1.0 / fact(17);
 constexpr double kC2 = -1.0 / fact(2), kC4 = 1.0 / fact(4), kC6 = -1.0 / fact(6), kC8 = 1.0 / fact(8);
 constexpr double kC10 = -1.0 / fact(10), kC12 = 1.0 / fact(12);
 

@@ -201,6 +201,27 @@ __device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& 
   return p;
 }
 
+// sin(theta) * w rounded to FP32, for any |theta| < 1.6e6: theta = k pi + x
+// with |x| <= pi/2 (Cody-Waite), sin(theta) = (-1)^k sin(x), sin(x) by its
+// Taylor series through x^17 (truncation below 1e-13 relative on the range).
+__device__ __forceinline__ float sin_over(double theta, double w) {
+  const double k = rint(theta * kOneOverPi);
+  double x = fma(-k, kPiA, theta);
+  x = fma(-k, kPiB, x);
+  x = fma(-k, kPiC, x);
+  const double x2 = x * x;
+  double p = add_vs(mul_vs(x2, kS17), kS15);
+  p = fma_vvs(p, x2, kS13);
+  p = fma_vvs(p, x2, kS11);
+  p = fma_vvs(p, x2, kS9);
+  p = fma_vvs(p, x2, kS7);
+  p = fma_vvs(p, x2, kS5);
+  p = fma_vvs(p, x2, kS3);
+  const double sx = fma(x * x2, p, x);
+  const float v = static_cast<float>(sx * w);
+  return __uint_as_float(__float_as_uint(v) ^ (static_cast<unsigned>(static_cast<int>(k)) << 31));
+}
+
 // Sum acc[0..64) over the 64 lanes; lane l receives the total of element l.
 // Recursive halving: at the step for lane bit b the lane keeps the half of its
 // live range selected by b and adds the partner's copy of that half.
@@ -234,7 +255,7 @@ __device__ __forceinline__ float lane_allreduce_tail(float* acc, int lane) {
   return mine;
 }
 
-template <int QC, int BJ>
+template <int QC, int BJ, bool DIRECT>
 __global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs a) {
   constexpr int NG = QC / kWave;          // full groups of 64 q values
   constexpr int R = QC % kWave;           // values in the tail group
@@ -266,6 +287,11 @@ __global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs
   __shared__ double tot[NT][kWave];
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
+  // direct form: this chunk's q values (0 past the end of the grid)
+  __shared__ double qv[DIRECT ? QC : 1];
+  if constexpr (DIRECT) {
+    for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
+  }
 
 #pragma unroll 1
   for (int J = sp.Ja; J < sp.Jb; ++J) {
@@ -292,6 +318,21 @@ __global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs
       float acc[QC];
 #pragma unroll
       for (int m = 0; m < QC; ++m) acc[m] = 0.f;
+      if constexpr (DIRECT) {
+        // arbitrary q grid: sin(q_m r)/r evaluated for every q, one pair per
+        // iteration (the q steps are independent of each other)
+#pragma unroll 1
+        for (int jl = sa; jl < sb; ++jl) {
+          const double4 pj = sj[jl - j0];
+          const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+          const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
+          const double ir = rsqrt_f64(r2);
+          const double r = r2 * ir;
+          const double w = (vi && jl > i) ? ir : 0.0;
+#pragma unroll
+          for (int m = 0; m < QC; ++m) acc[m] += sin_over(qv[m] * r, w);
+        }
+      } else {
       // two atom pairs (j, j+1) per iteration: two independent recurrence
       // chains give the scheduler work to issue while either waits on its
       // previous result; an odd segment ends with a masked partner
@@ -320,6 +361,7 @@ __global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs
           da = fmaf(A.nlam, za, da);
           db = fmaf(B.nlam, zb, db);
         }
+      }
       }
       // weight by this lane's f_a(q_m), sum over lanes, weight by f_b(q_m) in FP64
       // (the row pointer is laundered so that the loads stay here instead of
@@ -354,31 +396,39 @@ bool forward_qc_supported(int32_t qc) {
 }
 bool forward_bj_supported(int32_t bj) { return bj == 64 || bj == 128 || bj == 256 || bj == 512; }
 
-template <int QC>
+template <int QC, bool DIRECT>
 static hipError_t launch_forward_qc(const ForwardArgs& a, dim3 grid, hipStream_t st) {
   switch (a.geo.bj) {
-    case 64: hipLaunchKernelGGL((k_forward<QC, 64>), grid, dim3(kWave), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_forward<QC, 128>), grid, dim3(kWave), 0, st, a); break;
-    case 256: hipLaunchKernelGGL((k_forward<QC, 256>), grid, dim3(kWave), 0, st, a); break;
-    case 512: hipLaunchKernelGGL((k_forward<QC, 512>), grid, dim3(kWave), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_forward<QC, 64, DIRECT>), grid, dim3(kWave), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_forward<QC, 128, DIRECT>), grid, dim3(kWave), 0, st, a); break;
+    case 256: hipLaunchKernelGGL((k_forward<QC, 256, DIRECT>), grid, dim3(kWave), 0, st, a); break;
+    case 512: hipLaunchKernelGGL((k_forward<QC, 512, DIRECT>), grid, dim3(kWave), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+bool direct_qc_supported(int32_t qc) { return qc == 32; }
+
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st) {
   if (n_strips_total <= 0) return hipSuccess;
   const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
   const dim3 grid(static_cast<uint32_t>(n_strips_total), nchunks);
+  if (a.qdev) {
+    switch (qc_template) {
+      case 32: return launch_forward_qc<32, true>(a, grid, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (qc_template) {
-    case 16: return launch_forward_qc<16>(a, grid, st);
-    case 32: return launch_forward_qc<32>(a, grid, st);
-    case 50: return launch_forward_qc<50>(a, grid, st);
-    case 64: return launch_forward_qc<64>(a, grid, st);
-    case 100: return launch_forward_qc<100>(a, grid, st);
-    case 128: return launch_forward_qc<128>(a, grid, st);
-    case 150: return launch_forward_qc<150>(a, grid, st);
-    case 200: return launch_forward_qc<200>(a, grid, st);
+    case 16: return launch_forward_qc<16, false>(a, grid, st);
+    case 32: return launch_forward_qc<32, false>(a, grid, st);
+    case 50: return launch_forward_qc<50, false>(a, grid, st);
+    case 64: return launch_forward_qc<64, false>(a, grid, st);
+    case 100: return launch_forward_qc<100, false>(a, grid, st);
+    case 128: return launch_forward_qc<128, false>(a, grid, st);
+    case 150: return launch_forward_qc<150, false>(a, grid, st);
+    case 200: return launch_forward_qc<200, false>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -405,12 +455,13 @@ __global__ __launch_bounds__(256) void k_reduce_slices(DescView sd, const double
 __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double* __restrict__ slice_sums,
                                                       const int32_t* __restrict__ toff,
                                                       const float* __restrict__ table, int32_t T, int32_t Nq,
-                                                      double q0, double dq, double* __restrict__ I_out) {
+                                                      double q0, double dq, const double* __restrict__ qdev,
+                                                      double* __restrict__ I_out) {
   const int s = blockIdx.x;
   const StructDesc d = sd.get(s);
   const int32_t* o = toff + static_cast<int64_t>(s) * (T + 1);
   for (int m = threadIdx.x; m < Nq; m += blockDim.x) {
-    const double qm = q0 + m * dq;
+    const double qm = qdev ? qdev[m] : q0 + m * dq;
     double val;
     if (qm == 0.0) {
       double f = 0.0;
@@ -432,13 +483,14 @@ __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double*
 
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
                          double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
-                         double q0, double dq, double* I_out, hipStream_t st) {
+                         double q0, double dq, const double* qdev, double* I_out, hipStream_t st) {
   if (n_slices_total > 0) {
     hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total)), dim3(256), 0, st, sd, partial,
                        Nq, slice_sums);
   }
   if (S > 0) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(S), dim3(256), 0, st, sd, slice_sums, toff, table, T, Nq, q0, dq, I_out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(S), dim3(256), 0, st, sd, slice_sums, toff, table, T, Nq, q0, dq, qdev,
+                       I_out);
   }
   return hipGetLastError();
 }

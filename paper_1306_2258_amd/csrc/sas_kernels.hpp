@@ -52,7 +52,8 @@ struct ForwardArgs {
   int32_t T, Nq;
   int32_t ldt;          // row stride of tabp: (chunks-1)*qc + QC
   int32_t qc;           // q values per chunk (grid.y = number of chunks)
-  double q0, dq;
+  double q0, dq;        // uniform grid q_m = q0 + m dq (recurrence form)
+  const double* qdev;   // non-null: arbitrary grid [Nq] on the device (direct form)
 };
 
 constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
@@ -85,13 +86,14 @@ hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t l
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
                          double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
-                         double q0, double dq, double* I_out, hipStream_t st);
+                         double q0, double dq, const double* qdev, double* I_out, hipStream_t st);
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st);
 hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, const int32_t* perm, double* grad_out,
                               hipStream_t st);
 bool adjoint_bj_supported(int32_t bj);
 bool forward_qc_supported(int32_t qc);
+bool direct_qc_supported(int32_t qc);
 bool forward_bj_supported(int32_t bj);
 
 }  // namespace sas

@@ -264,9 +264,11 @@ def test_errors_are_reported(sd):
     say("error paths")
     m = W.random_molecule(991, 10, 5)
     c, t, tab = to_dev(m)
-    with pytest.raises(sd.SasError) as e:
-        sd.debye_profile(c, t, tab, np.array([0.0, 0.1, 0.3, 0.4, 0.5]))
-    assert e.value.status == 2
+    for bad in ([0.0, 0.2, 0.1, 0.4, 0.5], [-0.1, 0.1, 0.2, 0.3, 0.4], [0.0, 0.1, np.nan, 0.3, 0.4],
+                [0.0, 0.1, 0.1, 0.3, 0.4]):
+        with pytest.raises(sd.SasError) as e:
+            sd.debye_profile(c, t, tab, np.array(bad))
+        assert e.value.status == 2, bad
     ctx = sd.Context(0)
     n = m.n
     import ctypes

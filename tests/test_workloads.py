@@ -4,6 +4,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import pytest
 
 import workloads as W
 
@@ -89,3 +90,15 @@ def test_deterministic():
     r1 = W.random_molecule(5, 10, 4)
     r2 = W.random_molecule(5, 10, 4)
     assert np.array_equal(r1.coords, r2.coords)
+
+
+def test_non_uniform_grids():
+    g = W.log_grid(1e-3, 1.0, 150)
+    assert g[0] == pytest.approx(1e-3) and g[-1] == pytest.approx(1.0) and np.all(np.diff(g) > 0)
+    r = W.random_grid(5, 0.0, 1.0, 250)
+    assert r.dtype == np.float64 and len(r) == 250 and np.all(np.diff(r) > 0) and 0.0 <= r[0] and r[-1] <= 1.0
+    assert np.array_equal(r, W.random_grid(5, 0.0, 1.0, 250))
+    t = W.two_segment_grid(0.0, 0.1, 1.0, 40, 30)
+    assert len(t) == 70 and np.all(np.diff(t) > 0) and t[40] == 0.1 and t[-1] == 1.0
+    m = W.random_molecule(3, 10, 0, q=t)
+    assert m.table.shape == (5, 70) and np.array_equal(m.q, t)

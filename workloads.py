@@ -79,6 +79,29 @@ def q_grid(a: float, b: float, nq: int) -> np.ndarray:
     return np.linspace(a, b, nq, dtype=np.float64)
 
 
+# Non-uniform grids.  Measured SAS curves are often sampled on logarithmic
+# grids or on a fine low-q (Guinier) segment followed by a coarse one; these
+# exercise the direct evaluation path of the library.
+
+def log_grid(a: float, b: float, nq: int) -> np.ndarray:
+    """nq points geometrically spaced on [a, b], a > 0."""
+    return np.geomspace(a, b, nq, dtype=np.float64)
+
+
+def random_grid(seed: int, a: float, b: float, nq: int) -> np.ndarray:
+    """nq distinct sorted points drawn uniformly on [a, b]."""
+    rng = rng_for(seed)
+    while True:
+        q = np.sort(rng.uniform(a, b, size=nq))
+        if nq < 2 or np.all(np.diff(q) > 0):
+            return q.astype(np.float64)
+
+
+def two_segment_grid(a: float, mid: float, b: float, n1: int, n2: int) -> np.ndarray:
+    """n1 uniform points on [a, mid) then n2 uniform points on [mid, b]."""
+    return np.concatenate([np.linspace(a, mid, n1, endpoint=False), np.linspace(mid, b, n2)]).astype(np.float64)
+
+
 def gaussian_table(z, b, q) -> np.ndarray:
     """Rows f_t(q_m) = Z_t exp(-B_t q_m^2), evaluated in FP64 and rounded once to FP32.
 
@@ -227,11 +250,11 @@ def _rod(n: int, seed: int):
     return pts, types
 
 
-def dna_rod_50k(n: int = 50000, nq: int = 200, seed: int = BASE_SEED + 2) -> Molecule:
+def dna_rod_50k(n: int = 50000, nq: int = 200, seed: int = BASE_SEED + 2, q=None) -> Molecule:
     """50,000-atom double-helix rod (about 3,400 A long), 5 element types,
     200 q on [0, 1]."""
     pts, types = _rod(n, seed)
-    q = q_grid(0.0, 1.0, nq)
+    q = q_grid(0.0, 1.0, nq) if q is None else np.asarray(q, dtype=np.float64)
     return _finish("dna_rod_50k", pts.copy(), types.copy(), gaussian_table(TYPE_Z, TYPE_B, q), q)
 
 
@@ -287,14 +310,15 @@ WORKLOADS = {
 
 
 def random_molecule(seed: int, n: int, nq: int, t: int = 5, q0: float = 0.0, q1: float = 0.5, extent: float = 20.0,
-                    widths=None) -> Molecule:
+                    widths=None, q=None) -> Molecule:
     """Small generic case for edge tests: n atoms uniform in a cube of edge
     ``extent``, t types drawn uniformly, a table with Z_t = 1 + t and a
-    per-type Gaussian width (non-separable by default)."""
+    per-type Gaussian width (non-separable by default).  ``q`` replaces the
+    uniform grid (q0, q1, nq) when given."""
     rng = rng_for(seed)
     pts = rng.uniform(-extent / 2, extent / 2, size=(n, 3))
     types = rng.integers(0, t, size=n).astype(np.int32)
-    q = q_grid(q0, q1, nq)
+    q = q_grid(q0, q1, nq) if q is None else np.asarray(q, dtype=np.float64)
     z = 1.0 + np.arange(t, dtype=np.float64)
     if widths is None:
         widths = 0.5 + 0.25 * np.arange(t, dtype=np.float64)
