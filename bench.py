@@ -202,6 +202,10 @@ def main(argv=None):
             result["grad"] = bench_grad(sd, W, torch, dev)
         except Exception as exc:
             result["grad"] = {"error": str(exc)[:200]}
+        try:
+            result["direct"] = bench_direct(sd, W, torch, dev, ms_step)
+        except Exception as exc:
+            result["direct"] = {"error": str(exc)[:200]}
 
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -256,6 +260,34 @@ def bench_batched(sd, W, torch, dev):
     res["speedup_vs_plain"] = res["ms_plain_launches"] / best
     res["pair_q_per_s"] = work / (best / 1e3)
     log(f"batched {best:.3f} ms vs plain {res['ms_plain_launches']:.3f} ms")
+    return res
+
+
+def bench_direct(sd, W, torch, dev, ms_recurrence):
+    """The direct form (one sine per pair and q) on the 50,000-atom rod:
+    a 200-point log-spaced grid on [1e-3, 1], and the benchmark's uniform
+    grid forced into the direct form (what the recurrence saves)."""
+    res = {}
+    for label, m, form in (("log_grid_200", W.dna_rod_50k(q=W.log_grid(1e-3, 1.0, 200)), "auto"),
+                           ("uniform_grid_200_forced", W.dna_rod_50k(), "direct")):
+        coords = torch.from_numpy(m.coords).to(dev)
+        types = torch.from_numpy(m.types).to(dev)
+        table = torch.from_numpy(m.table).to(dev)
+        ctx = sd.Context(0)
+        ctx.set_form(form)
+        sd.debye_profile(coords, types, table, m.q, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.read_timing()
+        ctx.enable_timing(True)
+        ms = _time(lambda: sd.debye_profile(coords, types, table, m.q, ctx=ctx), torch)
+        ctx.enable_timing(False)
+        kt = ctx.read_timing()
+        kern_ms = kt["forward_ms"] / max(kt["forward_launches"], 1)
+        work = pair_q(m.n, m.q)
+        res[label] = {"form": ctx.form(), "ms": ms, "kernel_ms": kern_ms, "pair_q_per_s": work / (ms / 1e3),
+                      "kernel_pair_q_per_s": work / (kern_ms / 1e3)}
+        log(f"direct form {label}: {ms:.3f} ms (pair kernel {kern_ms:.3f} ms)")
+    res["recurrence_speedup"] = res["uniform_grid_200_forced"]["ms"] / ms_recurrence
     return res
 
 

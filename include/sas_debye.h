@@ -175,6 +175,21 @@ sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc);
 sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
 
 /*
+ * Evaluation form of the profile calls on ctx.  SAS_FORM_AUTO (the default)
+ * steps uniform grids by the recurrence and evaluates other grids directly;
+ * SAS_FORM_DIRECT evaluates every grid directly, one sine per pair and q as
+ * in the paper's per-q kernel (Implementation section), which measures what
+ * the recurrence saves.  sas_get_form reports the form the last profile call
+ * used: SAS_FORM_RECURRENCE or SAS_FORM_DIRECT.  The gradient always uses
+ * the recurrence.  Errors: SAS_ERR_INVALID_ARG (NULL, unknown form).
+ */
+#define SAS_FORM_AUTO 0
+#define SAS_FORM_DIRECT 1
+#define SAS_FORM_RECURRENCE 2
+sas_status sas_set_form(sas_ctx* ctx, int form);
+sas_status sas_get_form(const sas_ctx* ctx, int* form);
+
+/*
  * Kernel timing (optional, for benchmarks).  While enabled, every forward and
  * adjoint pair-kernel launch on ctx is bracketed by two HIP events recorded on
  * the launch stream.  sas_read_timing waits for those events, writes the

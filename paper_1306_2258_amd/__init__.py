@@ -96,6 +96,19 @@ class Context:
         check(load().sas_get_variant(self._h, ctypes.byref(bj), ctypes.byref(qc)), "sas_get_variant")
         return bj.value, qc.value
 
+    FORMS = {"auto": 0, "direct": 1}
+
+    def set_form(self, form: str = "auto") -> None:
+        """'direct' evaluates every grid by one sine per pair and q; 'auto'
+        (default) uses the recurrence on uniform grids."""
+        check(load().sas_set_form(self._h, self.FORMS[form]), "sas_set_form")
+
+    def form(self) -> str:
+        """Form the last profile call used: 'recurrence' or 'direct'."""
+        f = ctypes.c_int()
+        check(load().sas_get_form(self._h, ctypes.byref(f)), "sas_get_form")
+        return {1: "direct", 2: "recurrence"}[f.value]
+
     def enable_timing(self, on: bool = True) -> None:
         """Bracket every pair-kernel launch with HIP events on its stream."""
         check(load().sas_enable_timing(self._h, int(bool(on))), "sas_enable_timing")

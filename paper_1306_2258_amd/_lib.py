@@ -45,6 +45,8 @@ SIGNATURES = {
     "sas_debye_grad": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, P, P, P, P, SZ, P]),
     "sas_set_variant": (ctypes.c_int, [P, I32, I32]),
     "sas_get_variant": (ctypes.c_int, [P, P, P]),
+    "sas_set_form": (ctypes.c_int, [P, ctypes.c_int]),
+    "sas_get_form": (ctypes.c_int, [P, P]),
     "sas_enable_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "sas_read_timing": (ctypes.c_int, [P, P, P, P, P]),
 }

@@ -51,6 +51,8 @@ struct sas_ctx {
   int device = 0;
   int cu_count = 0;
   int32_t force_bj = 0, force_qc = 0;
+  bool force_direct = false;  // evaluate every grid by the direct form
+  bool last_direct = false;
   int32_t last_bj = 0, last_qc = 0;
   // pinned staging for the batched call's descriptor upload
   void* pinned = nullptr;
@@ -193,7 +195,10 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   sc.qc = qc;
   sc.nchunks = (Nq + qc - 1) / qc;
   sc.ldt = (sc.nchunks - 1) * qc + sc.qc_template;
-  int32_t bj = bj_override > 0 ? bj_override : (ctx && ctx->force_bj > 0 ? ctx->force_bj : default_bj(max_n));
+  // (the direct form's per-pair work is four times the recurrence's, so a
+  // 128-atom J block already amortises the per-segment lane reduction)
+  const int32_t auto_bj = direct ? std::min<int32_t>(default_bj(max_n), 128) : default_bj(max_n);
+  int32_t bj = bj_override > 0 ? bj_override : (ctx && ctx->force_bj > 0 ? ctx->force_bj : auto_bj);
   sc.geo.bj = bj;
   sc.geo.ib = sas::kWave;
   sc.geo.c = bj / sas::kWave;
@@ -515,6 +520,19 @@ sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc) {
   return SAS_OK;
 }
 
+sas_status sas_set_form(sas_ctx* ctx, int form) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  if (form != SAS_FORM_AUTO && form != SAS_FORM_DIRECT) return fail(SAS_ERR_INVALID_ARG, "unknown form %d", form);
+  ctx->force_direct = form == SAS_FORM_DIRECT;
+  return SAS_OK;
+}
+
+sas_status sas_get_form(const sas_ctx* ctx, int* form) {
+  if (!ctx || !form) return fail(SAS_ERR_INVALID_ARG, "NULL argument");
+  *form = ctx->last_direct ? SAS_FORM_DIRECT : SAS_FORM_RECURRENCE;
+  return SAS_OK;
+}
+
 sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc) {
   if (!ctx || !bj || !qc) return fail(SAS_ERR_INVALID_ARG, "NULL argument");
   *bj = ctx->last_bj;
@@ -581,7 +599,7 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   QGrid grid;
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform);
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -596,6 +614,7 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   if (st == SAS_OK) {
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
+    ctx->last_direct = sc.direct;
   }
   return st;
 }
@@ -630,7 +649,7 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   if (S == 0) return SAS_OK;
-  const Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform);
+  const Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform || ctx->force_direct);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -645,6 +664,7 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   if (st == SAS_OK) {
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
+    ctx->last_direct = sc.direct;
   }
   return st;
 }
@@ -663,6 +683,7 @@ struct sas_plan {
   int32_t T = 0, Nq = 0;
   std::vector<double> qh;  // the plan's own copy of the q grid
   QGrid grid;
+  bool direct = false;
   Schedule sc;
   Layout L;
   hipStream_t cap = nullptr;
@@ -692,7 +713,7 @@ sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
   SAS_HIP(hipEventCreate(&e1));
   sas_status status = SAS_OK;
   for (const auto& c : cands) {
-    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, !p->grid.uniform);
+    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, p->direct);
     const Layout L = make_layout(sc, p->T, p->Nq);
     if (L.total > p->ws_bytes) continue;
     status = upload_sync(sc, L, p->grid, p->ws);
@@ -748,7 +769,8 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   if (st != SAS_OK) return st;
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  const Schedule sc0 = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform);
+  const bool direct = !grid.uniform || ctx->force_direct;
+  const Schedule sc0 = make_schedule(ctx, sizes, t, nq, 0, 0, direct);
   const size_t need = make_layout(sc0, t, nq).total;
   if (ws_bytes < need) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, need);
   sas_plan* p = new (std::nothrow) sas_plan();
@@ -766,6 +788,7 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   p->qh.assign(q, q + nq);
   p->grid = grid;
   p->grid.host = p->qh.data();
+  p->direct = direct;
   *out = p;
   return SAS_OK;
 }
@@ -778,7 +801,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
   if (!p->ready) {
     // choose the tile shape: forced variant, cached choice, or timing
     int32_t bj = 0, qc = 0;
-    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->grid.uniform ? "u" : "d");
+    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->direct ? "d" : "u");
     const bool forced = p->ctx->force_bj > 0 || p->ctx->force_qc > 0;
     auto it = p->ctx->tuned.find(key);
     if (forced) {
@@ -791,7 +814,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
       if (st != SAS_OK) return st;
       p->ctx->tuned[key] = {bj, qc};
     }
-    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, !p->grid.uniform);
+    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, p->direct);
     p->L = make_layout(p->sc, p->T, p->Nq);
     if (p->L.total > p->ws_bytes)
       return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", p->ws_bytes, p->L.total);

@@ -36,7 +36,6 @@ struct SinCos {
 // truncation adds no measurable bias.
 constexpr double kS3 = -1.0 / fact(3), kS5 = 1.0 / fact(5), kS7 = -1.0 / fact(7), kS9 = 1.0 / fact(9);
 constexpr double kS11 = -1.0 / fact(11);
-constexpr double kS13 = 1.0 / fact(13), kS15 = -1.0 / fact(15), kS17 = 1.0 / fact(17);
 constexpr double kC2 = -1.0 / fact(2), kC4 = 1.0 / fact(4), kC6 = -1.0 / fact(6), kC8 = 1.0 / fact(8);
 constexpr double kC10 = -1.0 / fact(10), kC12 = 1.0 / fact(12);
 
@@ -108,6 +107,32 @@ __device__ __forceinline__ double rsqrt_f64(double a) {
 __device__ __forceinline__ float parity_sign(double k) {
   const unsigned bits = static_cast<unsigned>(static_cast<int>(k)) << 31;
   return __uint_as_float(bits ^ 0x3f800000u);
+}
+
+// Direct form: acc + sin(q r) * w, for any q >= 0, from rp = r / pi.
+// t = q * rp is rounded to the nearest integer k by adding 1.5 * 2^52 in the
+// same FMA (the sum's low word then holds k), x = t - k lies in [-1/2, 1/2]
+// and is exact to FP64 rounding, and sin(q r) = (-1)^k sin(pi x) =
+// sin(pi (-1)^k x): the parity of k flips the sign bit of x.  sin(pi x) is
+// x * P(x^2) with P the degree-4 minimax fit of relative error 5e-9
+// (coefficients rounded to FP32, 4e-8; fit_sinpi.py beside this file
+// reproduces them).  Four FP64 and eight FP32 instructions per call.
+constexpr double kRoundMagic = 0x1.8p+52;
+constexpr float kSinPi0 = 0x1.921fb6p+1f, kSinPi1 = -0x1.4abbc2p+2f, kSinPi2 = 0x1.4668b0p+1f,
+                kSinPi3 = -0x1.324ccap-1f, kSinPi4 = 0x1.3daff6p-4f;
+
+__device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
+  const double s = fma(q, rp, kRoundMagic);
+  const double k = s - kRoundMagic;
+  const float x = static_cast<float>(fma(q, rp, -k));
+  const unsigned lo = static_cast<unsigned>(__double2loint(s));
+  const float xs = __uint_as_float(__float_as_uint(x) + (lo << 31));
+  const float y = xs * xs;
+  float p = fmaf(y, kSinPi4, kSinPi3);
+  p = fmaf(p, y, kSinPi2);
+  p = fmaf(p, y, kSinPi1);
+  p = fmaf(p, y, kSinPi0);
+  return fmaf(xs * w, p, acc);
 }
 
 }  // namespace sas

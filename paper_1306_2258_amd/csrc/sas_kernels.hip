@@ -201,27 +201,6 @@ __device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& 
   return p;
 }
 
-// sin(theta) * w rounded to FP32, for any |theta| < 1.6e6: theta = k pi + x
-// with |x| <= pi/2 (Cody-Waite), sin(theta) = (-1)^k sin(x), sin(x) by its
-// Taylor series through x^17 (truncation below 1e-13 relative on the range).
-__device__ __forceinline__ float sin_over(double theta, double w) {
-  const double k = rint(theta * kOneOverPi);
-  double x = fma(-k, kPiA, theta);
-  x = fma(-k, kPiB, x);
-  x = fma(-k, kPiC, x);
-  const double x2 = x * x;
-  double p = add_vs(mul_vs(x2, kS17), kS15);
-  p = fma_vvs(p, x2, kS13);
-  p = fma_vvs(p, x2, kS11);
-  p = fma_vvs(p, x2, kS9);
-  p = fma_vvs(p, x2, kS7);
-  p = fma_vvs(p, x2, kS5);
-  p = fma_vvs(p, x2, kS3);
-  const double sx = fma(x * x2, p, x);
-  const float v = static_cast<float>(sx * w);
-  return __uint_as_float(__float_as_uint(v) ^ (static_cast<unsigned>(static_cast<int>(k)) << 31));
-}
-
 // Sum acc[0..64) over the 64 lanes; lane l receives the total of element l.
 // Recursive halving: at the step for lane bit b the lane keeps the half of its
 // live range selected by b and adds the partner's copy of that half.
@@ -256,7 +235,7 @@ __device__ __forceinline__ float lane_allreduce_tail(float* acc, int lane) {
 }
 
 template <int QC, int BJ, bool DIRECT>
-__global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs a) {
+__global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2 : 3)) void k_forward(ForwardArgs a) {
   constexpr int NG = QC / kWave;          // full groups of 64 q values
   constexpr int R = QC % kWave;           // values in the tail group
   constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
@@ -323,14 +302,17 @@ __global__ __launch_bounds__(kWave, QC > 128 ? 2 : 3) void k_forward(ForwardArgs
         // iteration (the q steps are independent of each other)
 #pragma unroll 1
         for (int jl = sa; jl < sb; ++jl) {
+          // (the q values are re-read from LDS for every pair rather than
+          // held in 64 VGPRs: four waves per SIMD instead of three)
+          asm volatile("" ::: "memory");
           const double4 pj = sj[jl - j0];
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
           const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
           const double ir = rsqrt_f64(r2);
-          const double r = r2 * ir;
-          const double w = (vi && jl > i) ? ir : 0.0;
+          const double rp = r2 * ir * kOneOverPi;
+          const float w = (vi && jl > i) ? static_cast<float>(ir) : 0.f;
 #pragma unroll
-          for (int m = 0; m < QC; ++m) acc[m] += sin_over(qv[m] * r, w);
+          for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w, acc[m]);
         }
       } else {
       // two atom pairs (j, j+1) per iteration: two independent recurrence

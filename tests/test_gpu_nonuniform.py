@@ -86,10 +86,30 @@ def test_direct_path_is_taken(sd):
     ctx = sd.Context(0)
     m = W.random_molecule(720, 300, 100, q0=0.0, q1=1.0, extent=20.0)
     gpu_profile(sd, m, ctx=ctx)
-    assert ctx.variant()[1] != 32
+    assert ctx.variant()[1] != 32 and ctx.form() == "recurrence"
     m2 = W.random_molecule(720, 300, 0, q=W.log_grid(1e-3, 1.0, 100), extent=20.0)
     gpu_profile(sd, m2, ctx=ctx)
-    assert ctx.variant()[1] == 32
+    assert ctx.variant()[1] == 32 and ctx.form() == "direct"
+
+
+@pytest.mark.parametrize("nq", [1, 2, 50, 200])
+def test_forced_direct_on_uniform_grid(sd, nq):
+    """The direct form on a uniform grid: the oracle's values, and the
+    recurrence's to the same tolerance."""
+    say(f"forced direct form on a uniform grid Nq={nq}")
+    m = W.random_molecule(725 + nq, 1200, nq, q0=0.0, q1=1.0, extent=40.0)
+    ctx = sd.Context(0)
+    rec = gpu_profile(sd, m, ctx=ctx)
+    assert ctx.form() == "recurrence"
+    ctx.set_form("direct")
+    e = check(sd, m, ctx=ctx)
+    assert ctx.form() == "direct"
+    got = gpu_profile(sd, m, ctx=ctx)
+    assert rel_err(got, rec).max() <= 2 * TOL
+    print(f"max rel err {e:.3e}")
+    ctx.set_form("auto")
+    gpu_profile(sd, m, ctx=ctx)
+    assert ctx.form() == "recurrence"
 
 
 def test_nearly_uniform_grid(sd):
