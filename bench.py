@@ -39,9 +39,11 @@ INSTR_PER_PAIR_Q = 3
 EXEC_FLOPS_PER_PAIR_Q = 4.0
 MIX_CYCLES_PER_WAVE_INSTR = 2.3
 ISSUE_CEILING_PAIR_Q = 1024 * 2.4e9 * 64 / (INSTR_PER_PAIR_Q * MIX_CYCLES_PER_WAVE_INSTR)
+BASE_SEED_PER_ATOM = 13062258 + 50
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1306_2258_amd", "csrc", f)
-                  for f in ("sas_kernels.hip", "sas_device.hpp", "sas_schedule.hpp", "sas_kernels.hpp")]
+                  for f in ("sas_kernels.hip", "sas_forward.hpp", "sas_device.hpp", "sas_schedule.hpp",
+                            "sas_kernels.hpp")]
 
 
 def kernel_source_hash() -> str:
@@ -206,6 +208,10 @@ def main(argv=None):
             result["direct"] = bench_direct(sd, W, torch, dev, ms_step)
         except Exception as exc:
             result["direct"] = {"error": str(exc)[:200]}
+        try:
+            result["per_atom"] = bench_per_atom(sd, W, torch, dev, ms_step)
+        except Exception as exc:
+            result["per_atom"] = {"error": str(exc)[:200]}
 
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -289,6 +295,30 @@ def bench_direct(sd, W, torch, dev, ms_recurrence):
         log(f"direct form {label}: {ms:.3f} ms (pair kernel {kern_ms:.3f} ms)")
     res["recurrence_speedup"] = res["uniform_grid_200_forced"]["ms"] / ms_recurrence
     return res
+
+
+def bench_per_atom(sd, W, torch, dev, ms_types):
+    """The 50,000-atom rod with one table row per atom (T = N = 50,000), on
+    the benchmark's 200-point grid: the per-atom form against the type-sorted
+    form of the headline."""
+    m = W.with_per_atom_factors(W.dna_rod_50k(), BASE_SEED_PER_ATOM)
+    coords = torch.from_numpy(m.coords).to(dev)
+    types = torch.from_numpy(m.types).to(dev)
+    table = torch.from_numpy(m.table).to(dev)
+    ctx = sd.Context(0)
+    sd.debye_profile(coords, types, table, m.q, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.enable_timing(True)
+    ms = _time(lambda: sd.debye_profile(coords, types, table, m.q, ctx=ctx), torch)
+    ctx.enable_timing(False)
+    kt = ctx.read_timing()
+    kern_ms = kt["forward_ms"] / max(kt["forward_launches"], 1)
+    work = pair_q(m.n, m.q)
+    bj, qc = ctx.variant()
+    log(f"per-atom form (T=N=50,000): {ms:.3f} ms (pair kernel {kern_ms:.3f} ms)")
+    return {"form": ctx.form(), "types": int(m.table.shape[0]), "variant": {"bj": bj, "qc": qc}, "ms": ms,
+            "kernel_ms": kern_ms, "pair_q_per_s": work / (ms / 1e3), "slowdown_vs_type_form": ms / ms_types}
 
 
 def bench_grad(sd, W, torch, dev):

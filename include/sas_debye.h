@@ -10,7 +10,11 @@
  *
  * Form factors are given per atom *type*: f_k(q_m) = table[type_k * Nq + m].
  * One type per atom reproduces the paper's per-atom form factors (the text
- * below Eq. 2); a handful of element types is the common case.
+ * below Eq. 2); a handful of element types is the common case.  With few
+ * types the atoms are sorted by type and f_a f_b is applied once per run of
+ * equal types; with many types (T > SAS_MAX_TYPES, or fewer than 16 atoms
+ * per type on average and T >= 64) every pair term is weighted by its f_j
+ * inside the q loop instead (the per-atom form), with the same accuracy.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -66,7 +70,8 @@ typedef enum {
 } sas_status;
 
 /* Limits of this version. */
-#define SAS_MAX_TYPES 4096          /* T                                           */
+#define SAS_MAX_TYPES 4096          /* T for sas_debye_grad and the type-sorted form */
+#define SAS_MAX_TABLE_TYPES (1 << 24) /* T for the profile calls (per-atom form above SAS_MAX_TYPES) */
 #define SAS_MAX_NQ 65536            /* Nq                                          */
 #define SAS_MAX_ATOMS 100000000LL   /* atoms per structure                         */
 
@@ -103,7 +108,7 @@ size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_
  *   types   dev  int32 [n]        type id of each atom, in [0, t)
  *   n                             number of atoms, 0 <= n <= SAS_MAX_ATOMS
  *   table   dev  float [t][nq]    f_type(q_m), row-major
- *   t                             number of types, 1 <= t <= SAS_MAX_TYPES
+ *   t                             number of types, 1 <= t <= SAS_MAX_TABLE_TYPES
  *   q       host double [nq]      q grid, uniform or not (see conventions)
  *   nq                            1 <= nq <= SAS_MAX_NQ
  *   I_out   dev  double [nq]      written: I(q_m)
@@ -156,7 +161,8 @@ void sas_plan_destroy(sas_plan* plan);
  *   dL_dI    dev double [nq]    weights (e.g. dchi2/dI)
  *   grad_out dev double [n][3]  written, in the caller's atom order
  *   I_out    dev double [nq] or NULL: if given, the profile is written too
- * q must be a uniform grid (SAS_ERR_Q_NOT_UNIFORM otherwise).
+ * q must be a uniform grid (SAS_ERR_Q_NOT_UNIFORM otherwise) and
+ * t <= SAS_MAX_TYPES (SAS_ERR_UNSUPPORTED otherwise).
  * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 1).
  */
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
@@ -175,17 +181,22 @@ sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc);
 sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
 
 /*
- * Evaluation form of the profile calls on ctx.  SAS_FORM_AUTO (the default)
- * steps uniform grids by the recurrence and evaluates other grids directly;
- * SAS_FORM_DIRECT evaluates every grid directly, one sine per pair and q as
- * in the paper's per-q kernel (Implementation section), which measures what
- * the recurrence saves.  sas_get_form reports the form the last profile call
- * used: SAS_FORM_RECURRENCE or SAS_FORM_DIRECT.  The gradient always uses
- * the recurrence.  Errors: SAS_ERR_INVALID_ARG (NULL, unknown form).
+ * Evaluation form of the profile calls on ctx, a combination of flags.
+ * SAS_FORM_AUTO (0, the default) steps uniform grids by the recurrence,
+ * evaluates other grids directly and picks the type-sorted or the per-atom
+ * form from T and the atom counts.  SAS_FORM_DIRECT evaluates every grid
+ * directly, one sine per pair and q as in the paper's per-q kernel
+ * (Implementation section), which measures what the recurrence saves.
+ * SAS_FORM_PER_ATOM weights every pair term by f_j inside the q loop even
+ * for few types.  sas_get_form reports the form the last profile call used:
+ * SAS_FORM_RECURRENCE or SAS_FORM_DIRECT, plus SAS_FORM_PER_ATOM when set.
+ * The gradient always uses the recurrence and the type-sorted form.
+ * Errors: SAS_ERR_INVALID_ARG (NULL, unknown flags).
  */
 #define SAS_FORM_AUTO 0
 #define SAS_FORM_DIRECT 1
 #define SAS_FORM_RECURRENCE 2
+#define SAS_FORM_PER_ATOM 4
 sas_status sas_set_form(sas_ctx* ctx, int form);
 sas_status sas_get_form(const sas_ctx* ctx, int* form);
 

@@ -96,18 +96,21 @@ class Context:
         check(load().sas_get_variant(self._h, ctypes.byref(bj), ctypes.byref(qc)), "sas_get_variant")
         return bj.value, qc.value
 
-    FORMS = {"auto": 0, "direct": 1}
+    FORMS = {"auto": 0, "direct": 1, "per_atom": 4, "direct+per_atom": 5}
 
     def set_form(self, form: str = "auto") -> None:
-        """'direct' evaluates every grid by one sine per pair and q; 'auto'
-        (default) uses the recurrence on uniform grids."""
+        """'direct' evaluates every grid by one sine per pair and q;
+        'per_atom' weights every pair term by f_j inside the q loop; 'auto'
+        (default) uses the recurrence on uniform grids and chooses between
+        the type-sorted and the per-atom form from T and the atom counts."""
         check(load().sas_set_form(self._h, self.FORMS[form]), "sas_set_form")
 
     def form(self) -> str:
-        """Form the last profile call used: 'recurrence' or 'direct'."""
+        """Form the last profile call used: 'recurrence' or 'direct', with
+        '+per_atom' appended for the per-atom form."""
         f = ctypes.c_int()
         check(load().sas_get_form(self._h, ctypes.byref(f)), "sas_get_form")
-        return {1: "direct", 2: "recurrence"}[f.value]
+        return ("direct" if f.value & 1 else "recurrence") + ("+per_atom" if f.value & 4 else "")
 
     def enable_timing(self, on: bool = True) -> None:
         """Bracket every pair-kernel launch with HIP events on its stream."""

@@ -16,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsas_debye.so")
-SOURCES = ["sas_kernels.hip", "sas_adjoint.hip", "sas_api.hip"]
+SOURCES = ["sas_kernels.hip", "sas_peratom.hip", "sas_adjoint.hip", "sas_api.hip"]
 ARCH = "gfx950"
 
 

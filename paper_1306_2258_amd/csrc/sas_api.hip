@@ -44,6 +44,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 const int32_t kQcTemplates[] = {16, 32, 50, 64, 100, 128, 150, 200};
+const int32_t kPaQcTemplates[] = {16, 32, 64, 100, 128, 200};
 
 }  // namespace
 
@@ -51,8 +52,9 @@ struct sas_ctx {
   int device = 0;
   int cu_count = 0;
   int32_t force_bj = 0, force_qc = 0;
-  bool force_direct = false;  // evaluate every grid by the direct form
-  bool last_direct = false;
+  bool force_direct = false;    // evaluate every grid by the direct form
+  bool force_per_atom = false;  // per-atom form factors whatever T
+  bool last_direct = false, last_per_atom = false;
   int32_t last_bj = 0, last_qc = 0;
   // pinned staging for the batched call's descriptor upload
   void* pinned = nullptr;
@@ -116,7 +118,8 @@ struct DeviceGuard {
 
 struct Schedule {
   Geometry geo{};
-  bool direct = false;  // arbitrary q grid: per-q evaluation instead of the recurrence
+  bool direct = false;    // arbitrary q grid: per-q evaluation instead of the recurrence
+  bool per_atom = false;  // f_j inside the pair loop, no type sort
   int32_t qc = 0, qc_template = 0;
   int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
   // adjoint (gradient) schedule, single structure only
@@ -133,6 +136,7 @@ struct Schedule {
 struct Layout {
   size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, tabp = 0, partial = 0, slices = 0;
   size_t gI = 0, gJ = 0, total = 0;
+  size_t asum = 0;  // per-atom form: per pack block sums of f and f^2
   // host-written block, uploaded in one copy: structure descriptors (S > 1)
   // followed by the q grid (direct form)
   size_t upload = 0, upload_bytes = 0, desc = 0, qdev = 0;
@@ -146,10 +150,31 @@ struct QGrid {
   bool uniform = false;
 };
 
-int32_t pick_qc_template(int32_t qc) {
+int32_t pick_qc_template(int32_t qc, bool per_atom) {
+  if (per_atom) {
+    for (int32_t t : kPaQcTemplates)
+      if (t >= qc) return t;
+    return 200;
+  }
   for (int32_t t : kQcTemplates)
     if (t >= qc) return t;
   return 200;
+}
+
+// The per-atom form when the table cannot go through the type sort, or when
+// the type segments would be short: with fewer than 16 atoms per type on
+// average, the per-segment lane reductions cost more than weighting every
+// pair term by f_j inside the q loop.
+int64_t max_size(const std::vector<int64_t>& sizes) {
+  int64_t m = 0;
+  for (int64_t n : sizes) m = std::max(m, n);
+  return m;
+}
+
+bool use_per_atom(const sas_ctx* ctx, int32_t T, int64_t max_n) {
+  if (T > SAS_MAX_TYPES) return true;
+  if (ctx && ctx->force_per_atom) return true;
+  return T >= 64 && max_n < 16LL * T;
 }
 
 // J-block size by the largest structure (measured on MI355X: 512 atoms for
@@ -164,9 +189,10 @@ int32_t default_bj(int64_t max_n) {
 
 // Build the schedule for structure sizes `sizes` (caller order).
 Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
-                       int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false) {
+                       int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false, bool per_atom = false) {
   Schedule sc;
   sc.direct = direct;
+  sc.per_atom = per_atom;
   sc.S = static_cast<int32_t>(sizes.size());
   int64_t max_n = 0;
   for (int64_t n : sizes) {
@@ -183,18 +209,24 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   } else if (qc_override > 0) {
     const int32_t nch = (Nq + qc_override - 1) / qc_override;
     qc = (Nq + nch - 1) / nch;
-    sc.qc_template = pick_qc_template(qc);
+    sc.qc_template = pick_qc_template(qc, per_atom);
   } else if (ctx && ctx->force_qc > 0) {
     qc = std::min(ctx->force_qc, Nq);
-    sc.qc_template = ctx->force_qc;
+    sc.qc_template = per_atom ? pick_qc_template(ctx->force_qc, true) : ctx->force_qc;
   } else {
     const int32_t nch = (Nq + 199) / 200;
     qc = (Nq + nch - 1) / nch;
-    sc.qc_template = pick_qc_template(qc);
+    sc.qc_template = pick_qc_template(qc, per_atom);
+  }
+  if (per_atom) {
+    // the per-atom form stages table rows as float4: chunk starts at
+    // multiples of 4 (every per-atom template is one)
+    qc = (qc + 3) / 4 * 4;
+    if (!direct) sc.qc_template = pick_qc_template(qc, true);
   }
   sc.qc = qc;
   sc.nchunks = (Nq + qc - 1) / qc;
-  sc.ldt = (sc.nchunks - 1) * qc + sc.qc_template;
+  sc.ldt = ((sc.nchunks - 1) * qc + sc.qc_template + 3) / 4 * 4;
   // (the direct form's per-pair work is four times the recurrence's, so a
   // 128-atom J block already amortises the per-segment lane reduction)
   const int32_t auto_bj = direct ? std::min<int32_t>(default_bj(max_n), 128) : default_bj(max_n);
@@ -292,8 +324,12 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   L.xyz = take(sizeof(double4) * sc.n_total);
   L.tsort = take(sizeof(int32_t) * sc.n_total);
   L.perm = take(sizeof(int32_t) * sc.n_total);
-  L.bcount = take(sizeof(int32_t) * sc.n_pack * T);
-  L.toff = take(sizeof(int32_t) * static_cast<size_t>(sc.S) * (T + 1));
+  if (sc.per_atom) {
+    L.asum = take(sizeof(double) * 2 * sc.n_pack * static_cast<size_t>(Nq));
+  } else {
+    L.bcount = take(sizeof(int32_t) * sc.n_pack * T);
+    L.toff = take(sizeof(int32_t) * static_cast<size_t>(sc.S) * (T + 1));
+  }
   {
     const size_t dbytes = sc.S > 1 ? align_up(sizeof(StructDesc) * sc.S) : 0;
     const size_t qbytes = sc.direct ? sizeof(double) * static_cast<size_t>(Nq) : 0;
@@ -314,10 +350,10 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   return L;
 }
 
-sas_status check_sizes(int64_t n, int32_t T, int32_t Nq) {
+sas_status check_sizes(int64_t n, int32_t T, int32_t Nq, int32_t max_types = SAS_MAX_TABLE_TYPES) {
   if (n < 0 || n > SAS_MAX_ATOMS) return fail(n < 0 ? SAS_ERR_INVALID_ARG : SAS_ERR_UNSUPPORTED, "atom count %lld outside [0, %lld]", (long long)n, (long long)SAS_MAX_ATOMS);
   if (T <= 0) return fail(SAS_ERR_INVALID_ARG, "type count %d must be >= 1", T);
-  if (T > SAS_MAX_TYPES) return fail(SAS_ERR_UNSUPPORTED, "type count %d above %d", T, SAS_MAX_TYPES);
+  if (T > max_types) return fail(SAS_ERR_UNSUPPORTED, "type count %d above %d", T, max_types);
   if (Nq <= 0) return fail(SAS_ERR_INVALID_ARG, "q count %d must be >= 1", Nq);
   if (Nq > SAS_MAX_NQ) return fail(SAS_ERR_UNSUPPORTED, "q count %d above %d", Nq, SAS_MAX_NQ);
   return SAS_OK;
@@ -414,15 +450,21 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   auto* partial = reinterpret_cast<double*>(w + L.partial);
   auto* slices = reinterpret_cast<double*>(w + L.slices);
   auto* tabp = reinterpret_cast<float*>(w + L.tabp);
+  auto* asum = sc.per_atom ? reinterpret_cast<double*>(w + L.asum) : nullptr;
   SAS_HIP(sas::launch_pad_table(table, T, Nq, sc.ldt, tabp, st));
-  SAS_HIP(sas::launch_pack(coords, types, sd, sc.S, sc.n_pack, T, bcount, toff, xyz, tsort, perm, st));
+  if (sc.per_atom) {
+    SAS_HIP(sas::launch_pack_plain(coords, types, sc.n_total, T, xyz, tsort, perm, st));
+    SAS_HIP(sas::launch_atom_sums(sd, sc.n_pack, tsort, tabp, T, sc.ldt, Nq, asum, st));
+  } else {
+    SAS_HIP(sas::launch_pack(coords, types, sd, sc.S, sc.n_pack, T, bcount, toff, xyz, tsort, perm, st));
+  }
   sas::ForwardArgs a;
   std::memset(&a, 0, sizeof(a));
   a.sd = sd;
   a.geo = sc.geo;
   a.xyz = xyz;
   a.tsort = tsort;
-  a.toff = toff;
+  a.toff = sc.per_atom ? nullptr : toff;
   a.tabp = tabp;
   a.ldt = sc.ldt;
   a.partial = partial;
@@ -434,9 +476,13 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   a.qdev = qdev;
   {
     LaunchTimer timer(ctx, st, false);
-    SAS_HIP(sas::launch_forward(a, sc.n_strips, sc.qc_template, st));
+    if (sc.per_atom)
+      SAS_HIP(sas::launch_forward_pa(a, sc.n_strips, sc.qc_template, st));
+    else
+      SAS_HIP(sas::launch_forward(a, sc.n_strips, sc.qc_template, st));
   }
-  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, toff, table, T, Nq, q0, dq, qdev, I_out, st));
+  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, sc.per_atom ? nullptr : toff, asum, table, T, Nq,
+                             q0, dq, qdev, I_out, st));
   return SAS_OK;
 }
 
@@ -522,14 +568,15 @@ sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc) {
 
 sas_status sas_set_form(sas_ctx* ctx, int form) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  if (form != SAS_FORM_AUTO && form != SAS_FORM_DIRECT) return fail(SAS_ERR_INVALID_ARG, "unknown form %d", form);
-  ctx->force_direct = form == SAS_FORM_DIRECT;
+  if (form & ~(SAS_FORM_DIRECT | SAS_FORM_PER_ATOM)) return fail(SAS_ERR_INVALID_ARG, "unknown form %d", form);
+  ctx->force_direct = (form & SAS_FORM_DIRECT) != 0;
+  ctx->force_per_atom = (form & SAS_FORM_PER_ATOM) != 0;
   return SAS_OK;
 }
 
 sas_status sas_get_form(const sas_ctx* ctx, int* form) {
   if (!ctx || !form) return fail(SAS_ERR_INVALID_ARG, "NULL argument");
-  *form = ctx->last_direct ? SAS_FORM_DIRECT : SAS_FORM_RECURRENCE;
+  *form = (ctx->last_direct ? SAS_FORM_DIRECT : SAS_FORM_RECURRENCE) | (ctx->last_per_atom ? SAS_FORM_PER_ATOM : 0);
   return SAS_OK;
 }
 
@@ -577,15 +624,19 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 }
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
-  if (check_sizes(n, t, nq) != SAS_OK) return 0;
+  if (check_sizes(n, t, nq, grad ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES) != SAS_OK) return 0;
   const std::vector<int64_t> sizes{n};
-  Schedule sc = make_schedule(ctx, sizes, t, nq);
   if (grad) {
-    add_adjoint(&sc, n, nq);  // the gradient needs a uniform grid
+    Schedule sc = make_schedule(ctx, sizes, t, nq);
+    add_adjoint(&sc, n, nq);  // the gradient needs a uniform grid and the type form
     return make_layout(sc, t, nq).total;
   }
-  // the grid is not known here: cover both the uniform and the direct form
-  return std::max(make_layout(sc, t, nq).total, make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, true), t, nq).total);
+  // the grid is not known here: cover the recurrence and the direct form
+  const bool pa = use_per_atom(ctx, t, n);
+  size_t need = 0;
+  for (bool direct : {false, true})
+    need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, direct, pa), t, nq).total);
+  return need;
 }
 
 sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
@@ -599,7 +650,8 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   QGrid grid;
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct);
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct,
+                                    use_per_atom(ctx, t, n));
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -615,6 +667,7 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
     ctx->last_direct = sc.direct;
+    ctx->last_per_atom = sc.per_atom;
   }
   return st;
 }
@@ -626,10 +679,12 @@ size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offse
   if (check_sizes(0, t, nq) != SAS_OK) return 0;
   // large enough for the automatic shape, every shape a plan may time, and
   // the direct form (the grid is not known here)
-  size_t need = make_layout(make_schedule(ctx, sizes, t, nq), t, nq).total;
+  const bool pa = use_per_atom(ctx, t, max_size(sizes));
+  size_t need = make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, false, pa), t, nq).total;
   for (const auto& c : tile_candidates(ctx, nq))
     for (bool direct : {false, true})
-      need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second, direct), t, nq).total);
+      need = std::max(need,
+                      make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second, direct, pa), t, nq).total);
   return need;
 }
 
@@ -649,7 +704,8 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   if (S == 0) return SAS_OK;
-  const Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform || ctx->force_direct);
+  const Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, !grid.uniform || ctx->force_direct,
+                                    use_per_atom(ctx, t, max_size(sizes)));
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -665,6 +721,7 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
     ctx->last_bj = sc.geo.bj;
     ctx->last_qc = sc.qc_template;
     ctx->last_direct = sc.direct;
+    ctx->last_per_atom = sc.per_atom;
   }
   return st;
 }
@@ -683,7 +740,7 @@ struct sas_plan {
   int32_t T = 0, Nq = 0;
   std::vector<double> qh;  // the plan's own copy of the q grid
   QGrid grid;
-  bool direct = false;
+  bool direct = false, per_atom = false;
   Schedule sc;
   Layout L;
   hipStream_t cap = nullptr;
@@ -713,7 +770,7 @@ sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
   SAS_HIP(hipEventCreate(&e1));
   sas_status status = SAS_OK;
   for (const auto& c : cands) {
-    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, p->direct);
+    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, p->direct, p->per_atom);
     const Layout L = make_layout(sc, p->T, p->Nq);
     if (L.total > p->ws_bytes) continue;
     status = upload_sync(sc, L, p->grid, p->ws);
@@ -770,7 +827,8 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
   const bool direct = !grid.uniform || ctx->force_direct;
-  const Schedule sc0 = make_schedule(ctx, sizes, t, nq, 0, 0, direct);
+  const bool per_atom = use_per_atom(ctx, t, max_size(sizes));
+  const Schedule sc0 = make_schedule(ctx, sizes, t, nq, 0, 0, direct, per_atom);
   const size_t need = make_layout(sc0, t, nq).total;
   if (ws_bytes < need) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, need);
   sas_plan* p = new (std::nothrow) sas_plan();
@@ -789,6 +847,7 @@ sas_status sas_plan_create_batched(sas_ctx* ctx, const float* coords, const int3
   p->grid = grid;
   p->grid.host = p->qh.data();
   p->direct = direct;
+  p->per_atom = per_atom;
   *out = p;
   return SAS_OK;
 }
@@ -801,7 +860,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
   if (!p->ready) {
     // choose the tile shape: forced variant, cached choice, or timing
     int32_t bj = 0, qc = 0;
-    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->direct ? "d" : "u");
+    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->direct ? "d" : "u") + (p->per_atom ? "a" : "t");
     const bool forced = p->ctx->force_bj > 0 || p->ctx->force_qc > 0;
     auto it = p->ctx->tuned.find(key);
     if (forced) {
@@ -814,7 +873,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
       if (st != SAS_OK) return st;
       p->ctx->tuned[key] = {bj, qc};
     }
-    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, p->direct);
+    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, p->direct, p->per_atom);
     p->L = make_layout(p->sc, p->T, p->Nq);
     if (p->L.total > p->ws_bytes)
       return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", p->ws_bytes, p->L.total);
@@ -857,7 +916,7 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
                           int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
                           double* I_out, void* workspace, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  sas_status st = check_sizes(n, t, nq);
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TYPES);
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types || !grad_out)) return fail(SAS_ERR_INVALID_ARG, "coords/types/grad_out is NULL");
   if (!table || !dL_dI) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI is NULL");

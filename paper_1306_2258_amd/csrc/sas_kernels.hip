@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "sas_device.hpp"
+#include "sas_forward.hpp"
 #include "sas_kernels.hpp"
 #include "sas_schedule.hpp"
 
@@ -149,90 +150,8 @@ hipError_t launch_pack(const float* coords, const int32_t* types, const DescView
 }
 
 // ---------------------------------------------------------------------------
-// Forward strips.
-//
-// For an atom pair at distance r and the chunk's grid theta_m = (q_s + m dq) r,
-// m = 0..nqc-1, the lane needs y_m = sin(theta_m)/r.  Write dq r = k pi + dp
-// with |dp| <= pi/2 and sigma = (-1)^k; then y_m = sigma^m z_m with
-// z_m = sin(q_s r + m dp)/r, and z obeys the second-order recurrence
-//     z_{m+1} = z_m + d_m,   d_{m+1} = d_m - lambda z_{m+1},
-// lambda = 4 sin^2(dp/2), in the difference form (Reinsch) that stays accurate
-// for small dp.  The seeds z_0 = sin(q_s r)/r and d_0 = z_1 - z_0 and lambda
-// come from FP64 trigonometry and are rounded to FP32 once.  Each q step then
-// costs three FP32 operations: the accumulate (sign folded in on odd steps),
-// z += d and d += -lambda z.  Coincident atoms (r = 0) use r^2 = 1e-60, for
-// which the same formulas give the sinc limit y_m = q_m.
+// Forward strips (recurrence and lane reductions: sas_forward.hpp).
 // ---------------------------------------------------------------------------
-// FP32 start of one pair's recurrence: z_0, d_0, -lambda and sigma (see
-// above), from the FP64 set-up.  `use` = 0 gives an all-zero sequence.
-struct PairSeed {
-  float z, d, nlam, sg;
-};
-
-__device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& pj, bool use, double dq, double qs) {
-  const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-  double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-  r2 = fmax(r2, 1e-60);
-  const double ir = rsqrt_f64(r2);
-  const double r = r2 * ir;
-  const double delta = dq * r;
-  const double k = rint(delta * kOneOverPi);
-  double dp = fma(-k, kPiA, delta);
-  dp = fma(-k, kPiB, dp);
-  dp = fma(-k, kPiC, dp);
-  const SinCos hh = sincos_small(0.5 * dp);
-  const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
-  const double lam = s2 * s2;     // 4 sin^2(dp/2) = 2 (1 - cos(dp))
-  const double sdp = s2 * hh.c;   // sin(dp)
-  PairSeed p;
-  p.nlam = static_cast<float>(-lam);
-  p.sg = parity_sign(k);
-  if (qs == 0.0) {
-    // chunk starting at q = 0: z_0 = 0, d_0 = sin(dp)/r
-    p.z = 0.f;
-    p.d = use ? static_cast<float>(sdp * ir) : 0.f;
-  } else {
-    const SinCos t0 = sincos_any(qs * r);
-    const double w = use ? ir : 0.0;
-    const double S0 = t0.s * w, C0 = t0.c * w;
-    p.z = static_cast<float>(S0);
-    p.d = static_cast<float>(fma(C0, sdp, -0.5 * lam * S0));
-  }
-  return p;
-}
-
-// Sum acc[0..64) over the 64 lanes; lane l receives the total of element l.
-// Recursive halving: at the step for lane bit b the lane keeps the half of its
-// live range selected by b and adds the partner's copy of that half.
-__device__ __forceinline__ float lane_transpose_reduce64(float* acc, int lane) {
-#pragma unroll
-  for (int step = 0; step < 6; ++step) {
-    const int half = 32 >> step;
-    const int bit = (lane >> (5 - step)) & 1;
-#pragma unroll
-    for (int k = 0; k < half; ++k) {
-      const float lo = acc[k], hi = acc[k + half];
-      const float send = bit ? lo : hi;
-      const float keep = bit ? hi : lo;
-      acc[k] = keep + __shfl_xor(send, half, kWave);
-    }
-  }
-  return acc[0];
-}
-
-// Sum acc[0..R) (R < 64) over the lanes; lane l < R receives element l.
-template <int R>
-__device__ __forceinline__ float lane_allreduce_tail(float* acc, int lane) {
-  float mine = 0.f;
-#pragma unroll
-  for (int k = 0; k < R; ++k) {
-    float v = acc[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-    mine = (lane == k) ? v : mine;
-  }
-  return mine;
-}
 
 template <int QC, int BJ, bool DIRECT>
 __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2 : 3)) void k_forward(ForwardArgs a) {
@@ -436,26 +355,36 @@ __global__ __launch_bounds__(256) void k_reduce_slices(DescView sd, const double
 
 __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double* __restrict__ slice_sums,
                                                       const int32_t* __restrict__ toff,
+                                                      const double* __restrict__ asum,
                                                       const float* __restrict__ table, int32_t T, int32_t Nq,
                                                       double q0, double dq, const double* __restrict__ qdev,
                                                       double* __restrict__ I_out) {
   const int s = blockIdx.x;
   const StructDesc d = sd.get(s);
-  const int32_t* o = toff + static_cast<int64_t>(s) * (T + 1);
+  const int32_t* o = toff ? toff + static_cast<int64_t>(s) * (T + 1) : nullptr;
+  const int64_t nb = ceil_div(d.n, kPackBlock);
   for (int m = threadIdx.x; m < Nq; m += blockDim.x) {
     const double qm = qdev ? qdev[m] : q0 + m * dq;
     double val;
     if (qm == 0.0) {
       double f = 0.0;
-      for (int t = 0; t < T; ++t) f += static_cast<double>(o[t + 1] - o[t]) * static_cast<double>(table[static_cast<int64_t>(t) * Nq + m]);
+      if (asum) {
+        for (int64_t k = 0; k < nb; ++k) f += asum[((d.pack_off + k) * 2 + 0) * Nq + m];
+      } else {
+        for (int t = 0; t < T; ++t) f += static_cast<double>(o[t + 1] - o[t]) * static_cast<double>(table[static_cast<int64_t>(t) * Nq + m]);
+      }
       val = f * f;
     } else {
       double pairs = 0.0;
       for (int64_t k = 0; k < d.n_slices; ++k) pairs += slice_sums[(d.slice_off + k) * Nq + m];
       double diag = 0.0;
-      for (int t = 0; t < T; ++t) {
-        const double f = table[static_cast<int64_t>(t) * Nq + m];
-        diag += static_cast<double>(o[t + 1] - o[t]) * f * f;
+      if (asum) {
+        for (int64_t k = 0; k < nb; ++k) diag += asum[((d.pack_off + k) * 2 + 1) * Nq + m];
+      } else {
+        for (int t = 0; t < T; ++t) {
+          const double f = table[static_cast<int64_t>(t) * Nq + m];
+          diag += static_cast<double>(o[t + 1] - o[t]) * f * f;
+        }
       }
       val = diag + (2.0 / qm) * pairs;
     }
@@ -464,15 +393,15 @@ __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double*
 }
 
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
-                         double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
-                         double q0, double dq, const double* qdev, double* I_out, hipStream_t st) {
+                         double* slice_sums, const int32_t* toff, const double* asum, const float* table, int32_t T,
+                         int32_t Nq, double q0, double dq, const double* qdev, double* I_out, hipStream_t st) {
   if (n_slices_total > 0) {
     hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total)), dim3(256), 0, st, sd, partial,
                        Nq, slice_sums);
   }
   if (S > 0) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(S), dim3(256), 0, st, sd, slice_sums, toff, table, T, Nq, q0, dq, qdev,
-                       I_out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(S), dim3(256), 0, st, sd, slice_sums, toff, asum, table, T, Nq, q0, dq,
+                       qdev, I_out);
   }
   return hipGetLastError();
 }

@@ -9,6 +9,7 @@ namespace sas {
 constexpr int kWave = 64;       // wavefront size on gfx950; one wave per forward work-group
 constexpr int kPackBlock = 256; // atoms per block of the pack (type sort) kernels
 constexpr int kSliceTiles = 256;  // strips summed by one first-level reduce work-group
+constexpr int kPaSub = 16;      // J atoms staged with their table rows at a time (per-atom form)
 
 // Per-structure schedule, in execution order (largest structure first).
 struct StructDesc {
@@ -84,9 +85,20 @@ hipError_t launch_pack(const float* coords, const int32_t* types, const DescView
                        int32_t* tsort, int32_t* perm, hipStream_t st);
 hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st);
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
+// Diagonal and q = 0 terms come from the type counts toff (type-segment form)
+// or, when asum is non-null, from the per-block sums of f and f^2 (per-atom
+// form: asum[pack block][2][Nq]).
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
-                         double* slice_sums, const int32_t* toff, const float* table, int32_t T, int32_t Nq,
-                         double q0, double dq, const double* qdev, double* I_out, hipStream_t st);
+                         double* slice_sums, const int32_t* toff, const double* asum, const float* table, int32_t T,
+                         int32_t Nq, double q0, double dq, const double* qdev, double* I_out, hipStream_t st);
+
+// Per-atom form (sas_peratom.hip).
+hipError_t launch_pack_plain(const float* coords, const int32_t* types, int64_t n_total, int32_t T, double4* xyz,
+                             int32_t* tsort, int32_t* perm, hipStream_t st);
+hipError_t launch_atom_sums(const DescView& sd, int64_t n_pack_blocks, const int32_t* tsort, const float* tabp,
+                            int32_t T, int32_t ldt, int32_t Nq, double* asum, hipStream_t st);
+hipError_t launch_forward_pa(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
+bool pa_qc_supported(int32_t qc);
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st);
 hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, const int32_t* perm, double* grad_out,

@@ -101,7 +101,10 @@ def test_workspace_queries(lib):
     assert lib.sas_debye_workspace_size(None, -1, 5, 64, 0) == 0
     assert lib.sas_debye_workspace_size(None, 10, 0, 64, 0) == 0
     assert lib.sas_debye_workspace_size(None, 10, 5, 0, 0) == 0
-    assert lib.sas_debye_workspace_size(None, 10, 5000, 8, 0) == 0  # T above the limit
+    # T above the type-sorted limit: profiles take the per-atom form, the gradient refuses
+    assert lib.sas_debye_workspace_size(None, 10, 5000, 8, 0) > 0
+    assert lib.sas_debye_workspace_size(None, 10, 5000, 8, 1) == 0
+    assert lib.sas_debye_workspace_size(None, 10, (1 << 24) + 1, 8, 0) == 0
     off = np.array([0, 500, 8500, 9000], dtype=np.int64)
     assert lib.sas_debye_workspace_size_batched(None, off.ctypes.data_as(ctypes.c_void_p), 3, 5, 100) > 0
     bad = np.array([0, 500, 400], dtype=np.int64)
@@ -132,3 +135,28 @@ def test_binding_q_grid_check():
     with pytest.raises(sd.SasError) as e:
         sd.q_grid_check([0.0, 0.5, 1.1])
     assert e.value.status == 2
+
+
+def test_sine_polynomial_constants_match_their_fit():
+    """The direct form's FP32 sine coefficients in sas_device.hpp are the ones
+    the committed Remez fit produces, and they reach 5e-8 relative on
+    |x| <= 1/2 (evaluated in FP64 here)."""
+    import importlib.util
+    import re
+
+    root = os.path.join(os.path.dirname(__file__), "..", "paper_1306_2258_amd", "csrc")
+    spec = importlib.util.spec_from_file_location("fit_sinpi", os.path.join(root, "fit_sinpi.py"))
+    fit = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fit)
+    coef, level = fit.remez()
+    assert level < 1e-8
+    src = open(os.path.join(root, "sas_device.hpp")).read()
+    found = {int(k): float.fromhex(v) for k, v in re.findall(r"kSinPi(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
+    assert sorted(found) == [0, 1, 2, 3, 4]
+    c32 = np.array([found[k] for k in range(5)])
+    assert np.array_equal(c32, coef.astype(np.float32).astype(np.float64))
+    x = np.linspace(-0.5, 0.5, 100001)
+    approx = x * np.polyval(c32[::-1], x * x)
+    exact = np.sin(np.pi * x)
+    nz = exact != 0
+    assert np.max(np.abs(approx[nz] - exact[nz]) / np.abs(exact[nz])) < 5e-8

@@ -1,0 +1,198 @@
+"""GPU parity of the per-atom form (one table row per atom, T = N) against the
+FP64 oracle.
+
+The per-atom form weights every pair term by f_j inside the q loop instead of
+sorting atoms by type; it is chosen automatically for tables with more rows
+than the type sort takes (T > 4096) or with fewer than 16 atoms per row on
+average, and can be forced.  Bar: max over q of |I_gpu - I_oracle| / I_oracle
+<= 1e-6, as for the other forms.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_2258_amd as mod
+
+    return mod
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(m):
+    import torch
+
+    return (torch.from_numpy(m.coords).cuda(), torch.from_numpy(m.types).cuda(), torch.from_numpy(m.table).cuda())
+
+
+def gpu_profile(sd, m, ctx=None):
+    c, t, tab = to_dev(m)
+    return sd.debye_profile(c, t, tab, m.q, ctx=ctx).cpu().numpy()
+
+
+def rel_err(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+def check(sd, m, ctx=None, pick=None):
+    got = gpu_profile(sd, m, ctx=ctx)
+    assert np.all(np.isfinite(got))
+    if pick is None:
+        ref = oracle.profile(m.coords, m.types, m.table, m.q)
+        err = rel_err(got, ref)
+    else:
+        ref = oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
+        err = rel_err(got[pick], ref)
+    assert err.max() <= TOL, f"{m.name}: max rel err {err.max():.3e} at {err.argmax()}"
+    return err.max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 15, 16, 17, 33, 63, 64, 65, 129, 700, 2000])
+def test_per_atom_table_sizes(sd, n):
+    say(f"per-atom table T=N={n}, 37 q")
+    m = W.with_per_atom_factors(W.random_molecule(800 + n, n, 37, q0=0.0, q1=1.0,
+                                                  extent=3.0 * max(n, 1) ** (1 / 3) + 2.0), 900 + n)
+    ctx = sd.Context(0)
+    e = check(sd, m, ctx=ctx)
+    if n >= 64:
+        assert ctx.form() == "recurrence+per_atom"
+    print(f"max rel err {e:.3e} form {ctx.form()}")
+
+
+@pytest.mark.parametrize("nq", [1, 2, 17, 64, 100, 129, 200, 250])
+def test_per_atom_q_counts(sd, nq):
+    say(f"per-atom table, Nq={nq}")
+    m = W.with_per_atom_factors(W.random_molecule(820 + nq, 500, nq, q0=0.0, q1=0.9, extent=24.0), 921 + nq)
+    check(sd, m)
+
+
+@pytest.mark.parametrize("q0", [1e-3, 0.3])
+def test_per_atom_grid_start(sd, q0):
+    say(f"per-atom table, grid starting at q0={q0}")
+    m = W.with_per_atom_factors(W.random_molecule(840, 600, 45, q0=q0, q1=q0 + 0.7, extent=26.0), 940)
+    check(sd, m)
+
+
+def test_forced_per_atom_on_few_types(sd):
+    """Forced per-atom form on a five-type molecule: the oracle's values and
+    the type-sorted form's to the same tolerance."""
+    say("forced per-atom form, T=5")
+    m = W.random_molecule(850, 1500, 80, q0=0.0, q1=1.0, extent=40.0)
+    ctx = sd.Context(0)
+    typed = gpu_profile(sd, m, ctx=ctx)
+    assert ctx.form() == "recurrence"
+    ctx.set_form("per_atom")
+    check(sd, m, ctx=ctx)
+    assert ctx.form() == "recurrence+per_atom"
+    pa = gpu_profile(sd, m, ctx=ctx)
+    assert rel_err(pa, typed).max() <= 2 * TOL
+
+
+def test_per_atom_direct_nonuniform(sd):
+    say("per-atom table on a log-spaced grid (direct + per-atom)")
+    m = W.with_per_atom_factors(W.random_molecule(860, 900, 0, q=W.log_grid(1e-3, 1.0, 70), extent=30.0), 960)
+    ctx = sd.Context(0)
+    check(sd, m, ctx=ctx)
+    assert ctx.form() == "direct+per_atom"
+
+
+def test_per_atom_coincident_and_large_q(sd):
+    say("per-atom table: coincident atoms, theta up to ~2e4 rad")
+    m = W.with_per_atom_factors(W.random_molecule(870, 400, 30, q0=0.0, q1=5.0, extent=4000.0), 970)
+    m.coords[7] = m.coords[3]
+    m.coords[399] = m.coords[0]
+    check(sd, m)
+
+
+@pytest.mark.parametrize("bj", [64, 128, 256, 512])
+def test_per_atom_variants_and_determinism(sd, bj):
+    say(f"per-atom table, forced bj={bj}, two calls bitwise equal")
+    ctx = sd.Context(0)
+    ctx.set_variant(bj, 0)
+    m = W.with_per_atom_factors(W.random_molecule(880, 1700, 60, q0=0.0, q1=1.0, extent=36.0), 980)
+    check(sd, m, ctx=ctx)
+    a = gpu_profile(sd, m, ctx=ctx)
+    b = gpu_profile(sd, m, ctx=ctx)
+    assert np.array_equal(a, b)
+    assert ctx.variant()[0] == bj
+
+
+def test_more_rows_than_the_type_sort_takes(sd):
+    """6,000 atoms with 6,000 table rows (above 4,096): profiles take the
+    per-atom form; the gradient refuses the table (status 3)."""
+    import torch
+
+    say("T = N = 6000 > 4096")
+    m = W.with_per_atom_factors(W.random_molecule(890, 6000, 40, q0=0.0, q1=0.8, extent=45.0), 990)
+    ctx = sd.Context(0)
+    check(sd, m, ctx=ctx, pick=np.array([0, 1, 13, 27, 39]))
+    assert ctx.form() == "recurrence+per_atom"
+    c, t, tab = to_dev(m)
+    with pytest.raises(sd.SasError) as e:
+        sd.debye_grad(c, t, tab, m.q, torch.ones(40, dtype=torch.float64, device="cuda"))
+    assert e.value.status == 3
+
+
+def test_per_atom_batched_and_plan(sd):
+    import torch
+
+    say("per-atom tables, batched call and plan replays")
+    sizes = [700, 0, 1, 65, 1300, 2, 64]
+    q = W.q_grid(0.0, 0.8, 50)
+    mols = [W.random_molecule(1000 + k, n, 50, q0=0.0, q1=0.8, extent=2.5 * max(n, 1) ** (1 / 3) + 3)
+            for k, n in enumerate(sizes)]
+    coords = np.concatenate([mm.coords for mm in mols]).astype(np.float32)
+    base_types = np.concatenate([mm.types for mm in mols]).astype(np.int32)
+    big = W.Molecule("ens", coords, base_types, mols[0].table, q)
+    pa = W.with_per_atom_factors(big, 1100)
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    c, t, tab = (torch.from_numpy(a).cuda() for a in (pa.coords, pa.types, pa.table))
+    ctx = sd.Context(0)
+    ctx.set_variant(128, 0)
+    out = sd.debye_profile_batched(c, t, off, tab, q, ctx=ctx).cpu().numpy()
+    for k, n in enumerate(sizes):
+        a, b = off[k], off[k + 1]
+        if n == 0:
+            assert np.all(out[k] == 0.0)
+            continue
+        ref = oracle.profile(pa.coords[a:b], pa.types[a:b], pa.table, q)
+        assert rel_err(out[k], ref).max() <= TOL, f"structure {k} (N={n})"
+        plain = gpu_profile(sd, W.Molecule("p", pa.coords[a:b], pa.types[a:b], pa.table, q), ctx=ctx)
+        assert np.array_equal(out[k], plain), f"structure {k}"
+    plan = sd.BatchedPlan(c, t, off, tab, q, ctx=ctx)
+    for rep in range(2):
+        got = plan.execute().clone()
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), out), f"replay {rep}"
+    plan.close()
+
+
+def test_globular_10k_per_atom_sampled(sd):
+    """The 10,000-atom globular workload with per-atom factors (T = N), five q
+    values against the oracle."""
+    say("globular_10k with per-atom factors, N=T=10000, Nq=100")
+    m = W.with_per_atom_factors(W.globular_10k(), 1200)
+    ctx = sd.Context(0)
+    e = check(sd, m, ctx=ctx, pick=np.array([0, 1, 33, 66, 99]))
+    assert ctx.form() == "recurrence+per_atom"
+    print(f"max rel err {e:.3e}")

@@ -102,3 +102,14 @@ def test_non_uniform_grids():
     assert len(t) == 70 and np.all(np.diff(t) > 0) and t[40] == 0.1 and t[-1] == 1.0
     m = W.random_molecule(3, 10, 0, q=t)
     assert m.table.shape == (5, 70) and np.array_equal(m.q, t)
+
+
+def test_per_atom_factors():
+    m = W.random_molecule(7, 50, 12, q0=0.0, q1=0.6)
+    p = W.with_per_atom_factors(m, 3)
+    assert p.table.shape == (50, 12) and p.types.dtype == np.int32
+    assert sorted(p.types.tolist()) == list(range(50))
+    # atom i's row is its element row scaled by 1 + 0.1 (a + b q/qmax), |.| <= 0.2
+    ratio = p.table[p.types].astype(np.float64) / m.table[m.types].astype(np.float64)
+    assert np.all(np.abs(ratio - 1.0) <= 0.2 + 1e-6)
+    assert np.array_equal(p.coords, m.coords)

@@ -301,6 +301,26 @@ def lattice_20k(n: int = 20000, nq: int = 100, seed: int = BASE_SEED + 4, pertur
     return _finish("lattice_20k", pts, types, table, q, target_coords=np.ascontiguousarray(tgt, dtype=np.float32))
 
 
+def with_per_atom_factors(m: Molecule, seed: int, spread: float = 0.1, shuffle: bool = True) -> Molecule:
+    """The same atoms with one table row per atom (T = N): atom i's element
+    factor scaled by 1 + spread (a_i + b_i q / q_max), a_i, b_i ~ U(-1, 1), the
+    kind of per-atom correction a hydration or excluded-volume model applies.
+    With ``shuffle`` the row of atom i is a random permutation index, so that
+    atom order and row order differ."""
+    rng = rng_for(seed)
+    n = m.n
+    a = rng.uniform(-1.0, 1.0, size=n)
+    b = rng.uniform(-1.0, 1.0, size=n)
+    qmax = max(float(np.max(m.q)), 1e-30) if len(m.q) else 1.0
+    rows = rng.permutation(n).astype(np.int32) if shuffle else np.arange(n, dtype=np.int32)
+    scale = 1.0 + spread * (a[:, None] + b[:, None] * (m.q[None, :] / qmax))
+    per_atom = m.table.astype(np.float64)[m.types] * scale  # row i belongs to atom i
+    table = np.empty_like(per_atom)
+    table[rows] = per_atom
+    return Molecule(m.name + "_per_atom", m.coords, rows, np.ascontiguousarray(table, dtype=np.float32), m.q,
+                    dict(m.extra))
+
+
 WORKLOADS = {
     "ellipsoid_1k": ellipsoid_1k,
     "globular_10k": globular_10k,
