@@ -32,15 +32,17 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, 256 CU x 2.4 GHz x 256 flop/clk
 FLOPS_PER_PAIR_Q = 10.0   # forward: 4 FMA rotation + 1 FMA accumulate (the metric's convention)
 FLOPS_PER_PAIR_Q_ADJ = 12.0
-# What the forward pair loop really issues per pair*q: v_add_f32 x2 + v_fmac_f32 x1
-# (4 flops), and the issue cost of that mix measured on MI355X with a
-# microbenchmark: 2.3 cycles per wave64 instruction (1024 SIMDs, 2.4 GHz).
+# What the forward pair loop really issues per pair*q: three instructions, on
+# average 1.5 v_add_f32 + 1.5 v_fma(c)_f32 (4.5 flops; the VALU counters agree),
+# and the issue cost of that mix measured on MI355X with a microbenchmark:
+# 2.3 cycles per wave64 instruction (1024 SIMDs, 2.4 GHz).
 INSTR_PER_PAIR_Q = 3
-EXEC_FLOPS_PER_PAIR_Q = 4.0
+EXEC_FLOPS_PER_PAIR_Q = 4.5
 MIX_CYCLES_PER_WAVE_INSTR = 2.3
 ISSUE_CEILING_PAIR_Q = 1024 * 2.4e9 * 64 / (INSTR_PER_PAIR_Q * MIX_CYCLES_PER_WAVE_INSTR)
 BASE_SEED_PER_ATOM = 13062258 + 50
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_valu.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1306_2258_amd", "csrc", f)
                   for f in ("sas_kernels.hip", "sas_forward.hpp", "sas_device.hpp", "sas_schedule.hpp",
                             "sas_kernels.hpp")]
@@ -56,23 +58,47 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel_name: str):
-    """HBM bytes per pair-kernel launch from the committed --pmc summary, or
-    None when it is missing or was taken on different kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def stored_counters(path: str, kernel_name: str):
+    """key = value lines of a committed --pmc summary, or None when it is
+    missing or was taken on different kernel sources or another kernel."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_sha256") != kernel_source_hash() or kv.get("kernel") != kernel_name:
         return None
+    return kv
+
+
+def stored_traffic(kernel_name: str):
+    """HBM bytes per pair-kernel launch from the committed FETCH/WRITE summary."""
+    kv = stored_counters(TRAFFIC_FILE, kernel_name)
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def stored_valu(kernel_name: str, work: float, kern_ms: float):
+    """Executed FP32 rate and VALU issue figures from the committed VALU
+    counter summary, scaled to this run's measured kernel time."""
+    kv = stored_counters(VALU_FILE, kernel_name)
+    if not kv:
+        return None
+    try:
+        flops = float(kv["SQ_INSTS_VALU_FLOPS_FP32"]) * 64.0
+        insts = float(kv["SQ_INSTS_VALU"])
+    except (KeyError, ValueError):
+        return None
+    tflops = flops / (kern_ms / 1e3) / 1e12
+    return {"executed_fp32_flops_per_pair_q": flops / work, "executed_fp32_tflops": tflops,
+            "frac_of_fp32_peak": tflops / PEAK_FP32_TFLOPS, "valu_insts_per_pair_q": insts * 64.0 / work,
+            "cycles_per_valu_inst_per_simd": (kern_ms / 1e3) * 2.4e9 / (insts / 1024.0),
+            "source": os.path.relpath(VALU_FILE, ROOT)}
 
 
 def log(msg):
@@ -181,7 +207,8 @@ def main(argv=None):
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(kname),
                      "kernel": kname, "kernel_ms": kern_ms, "flops_per_pair_q": FLOPS_PER_PAIR_Q,
                      "executed_fp32_tflops": EXEC_FLOPS_PER_PAIR_Q * work / (kern_ms / 1e3) / 1e12,
-                     "issue_frac": (work / (kern_ms / 1e3)) / ISSUE_CEILING_PAIR_Q},
+                     "issue_frac": (work / (kern_ms / 1e3)) / ISSUE_CEILING_PAIR_Q,
+                     "valu_counters": stored_valu(kname, work, kern_ms)},
     }
 
     # accuracy of the timed output against the stored FP64 oracle profile
