@@ -363,9 +363,20 @@ def bench_grad(sd, W, torch, dev):
     ms_grad = _time(lambda: sd.debye_grad(coords, types, table, m.q, w, with_profile=True, ctx=ctx), torch)
     work = pair_q(m.n, m.q)
     log(f"grad {ms_grad:.3f} ms vs forward {ms_fwd:.3f} ms")
-    return {"atoms": m.n, "nq": len(m.q), "ms_forward": ms_fwd, "ms_forward_plus_adjoint": ms_grad,
-            "ratio": ms_grad / ms_fwd, "fd_equivalent_speedup": 6 * m.n * ms_fwd / ms_grad,
-            "adjoint_tflops_alg": FLOPS_PER_PAIR_Q_ADJ * work / (ms_grad / 1e3) / 1e12}
+    res = {"atoms": m.n, "nq": len(m.q), "ms_forward": ms_fwd, "ms_forward_plus_adjoint": ms_grad,
+           "ratio": ms_grad / ms_fwd, "fd_equivalent_speedup": 6 * m.n * ms_fwd / ms_grad,
+           "adjoint_tflops_alg": FLOPS_PER_PAIR_Q_ADJ * work / (ms_grad / 1e3) / 1e12}
+    # the same lattice on a 100-point log-spaced grid: direct forward + direct adjoint
+    ql = W.log_grid(1e-3, 0.5, 100)
+    tab_l = torch.from_numpy(W.gaussian_table((10.0,), 2.0, ql)).to(dev)
+    fwd_l = sd.debye_profile(coords, types, tab_l, ql, ctx=ctx)
+    w_l = 2.0 * (fwd_l - fwd_l * 1.01) / (0.01 * fwd_l * 1.01) ** 2
+    ms_fwd_l = _time(lambda: sd.debye_profile(coords, types, tab_l, ql, ctx=ctx), torch)
+    ms_grad_l = _time(lambda: sd.debye_grad(coords, types, tab_l, ql, w_l, with_profile=True, ctx=ctx), torch)
+    log(f"grad on a log grid {ms_grad_l:.3f} ms vs forward {ms_fwd_l:.3f} ms")
+    res["log_grid_100"] = {"ms_forward": ms_fwd_l, "ms_forward_plus_adjoint": ms_grad_l,
+                           "ratio": ms_grad_l / ms_fwd_l}
+    return res
 
 
 if __name__ == "__main__":

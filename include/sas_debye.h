@@ -33,8 +33,8 @@
  *    Results section evaluates profiles on such grids; Nq <= 2 always counts
  *    as uniform) takes the fast path: the pair kernel steps sin(q r) from one
  *    q to the next by a recurrence.  Any other grid is evaluated directly,
- *    one sine per pair and q, at a few times the cost per pair and q.  The
- *    profile calls accept both; sas_debye_grad needs a uniform grid.
+ *    one sine per pair and q, at a few times the cost per pair and q.  Every
+ *    call accepts both.
  *  - Results are FP64.  Pair terms are evaluated in FP32 from FP64 per-pair
  *    set-up values; every cross-lane and cross-block sum beyond one 64-lane
  *    wave is FP64 and in a fixed order, so two identical calls give bitwise
@@ -161,8 +161,10 @@ void sas_plan_destroy(sas_plan* plan);
  *   dL_dI    dev double [nq]    weights (e.g. dchi2/dI)
  *   grad_out dev double [n][3]  written, in the caller's atom order
  *   I_out    dev double [nq] or NULL: if given, the profile is written too
- * q must be a uniform grid (SAS_ERR_Q_NOT_UNIFORM otherwise) and
- * t <= SAS_MAX_TYPES (SAS_ERR_UNSUPPORTED otherwise).
+ * q follows the profile's conventions: a uniform grid takes the recurrence,
+ * any other increasing grid the direct variant (sin and cos of q r evaluated
+ * for every pair and q, about four times the cost).  t <= SAS_MAX_TYPES
+ * (SAS_ERR_UNSUPPORTED otherwise).
  * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 1).
  */
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
@@ -190,7 +192,8 @@ sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
  * SAS_FORM_PER_ATOM weights every pair term by f_j inside the q loop even
  * for few types.  sas_get_form reports the form the last profile call used:
  * SAS_FORM_RECURRENCE or SAS_FORM_DIRECT, plus SAS_FORM_PER_ATOM when set.
- * The gradient always uses the recurrence and the type-sorted form.
+ * The gradient uses the type-sorted form, and the direct variant exactly
+ * when the grid is not uniform.
  * Errors: SAS_ERR_INVALID_ARG (NULL, unknown flags).
  */
 #define SAS_FORM_AUTO 0

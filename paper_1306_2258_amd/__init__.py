@@ -17,7 +17,7 @@ types   int32   [N]    on the GPU, values in [0, T)
 table   float32 [T, Nq] on the GPU: f_type(q_m)
 q       1-D float64 host array / list / CPU tensor (1/Angstrom): finite,
         >= 0, strictly increasing; uniform grids take the recurrence path,
-        other grids are evaluated directly (the gradient needs uniform q)
+        other grids are evaluated directly
 results float64 on the GPU
 """
 from __future__ import annotations
@@ -262,7 +262,8 @@ class BatchedPlan:
 def debye_grad(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, dL_dI: torch.Tensor, *,
                with_profile: bool = False, ctx: Optional[Context] = None):
     """sum_m dL_dI[m] dI(q_m)/dcoords as float64 [N, 3] (and the profile if
-    ``with_profile``); q must be a uniform grid."""
+    ``with_profile``); any increasing grid (non-uniform ones take the direct
+    variant)."""
     _check_inputs(coords, types, table)
     ctx = ctx or default_context(coords.device)
     qh = _q_host(q)

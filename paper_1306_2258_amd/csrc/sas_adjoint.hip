@@ -20,6 +20,11 @@
 // the j-side sums (both atoms of a lane added first) are reduced over the 64
 // lanes per j with DPP row operations and kept in FP64 in LDS.
 // Partial sums go to per-strip rows that a second kernel adds in fixed order.
+//
+// A non-uniform q grid has no recurrence: the direct variant evaluates sin and
+// cos of q_m r for every q (FP64 reduction of q r / pi, FP32 polynomials, as
+// in the forward's direct form) and accumulates C and S with their signs,
+// two FMAs per atom and q.
 #include <hip/hip_runtime.h>
 
 #include "sas_device.hpp"
@@ -106,12 +111,18 @@ __device__ __forceinline__ double adj_force(const AdjSeed& p, float a1e, float a
   return p.valid ? 2.0 * p.ir * p.ir * (Cc - A3 * p.ir) : 0.0;
 }
 
-template <int BJ>
+// G of one atom of the direct variant from its sums C and S.
+__device__ __forceinline__ double adj_force_direct(bool valid, double ir, float c, float s) {
+  return valid ? 2.0 * ir * ir * (static_cast<double>(c) - static_cast<double>(s) * ir) : 0.0;
+}
+
+template <int BJ, bool DIRECT>
 __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   __shared__ double4 sj[BJ];
   __shared__ float4 ul4[kAdjQ / 4];
   __shared__ float4 vl4[kAdjQ / 4];
   __shared__ double gjl[BJ * 3];
+  __shared__ double qvl[DIRECT ? kAdjQ : 1];
   float* ul = reinterpret_cast<float*>(ul4);
   float* vl = reinterpret_cast<float*>(vl4);
 
@@ -175,7 +186,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
         const float* fb = a.tabp + static_cast<int64_t>(tb) * a.ldt + m0;
         for (int m = lane; m < nq8; m += kWave) {
           float u = 0.f, v = 0.f;
-          const double qm = a.q0 + (m0 + m) * dq;
+          const double qm = DIRECT ? (m < nqa ? a.qdev[m0 + m] : 0.0) : a.q0 + (m0 + m) * dq;
           if (m < nqa && qm > 0.0) {
             const double uu = a.w[m0 + m] * static_cast<double>(fa[m]) * static_cast<double>(fb[m]);
             u = static_cast<float>(uu);
@@ -183,9 +194,55 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
           }
           ul[m] = u;
           vl[m] = v;
+          if constexpr (DIRECT) qvl[m] = qm;
         }
         __syncthreads();
         const float u0 = ul[0];
+        if constexpr (DIRECT) {
+#pragma unroll 1
+          for (int jl = sa; jl < sb; ++jl) {
+            const double4 pj = sj[jl - j0];
+            const double ax = p1.x - pj.x, ay = p1.y - pj.y, az = p1.z - pj.z;
+            const double bx = p2.x - pj.x, by = p2.y - pj.y, bz = p2.z - pj.z;
+            const double ra2 = fma(az, az, fma(ay, ay, ax * ax));
+            const double rb2 = fma(bz, bz, fma(by, by, bx * bx));
+            const bool va = mine1 && jl > i1 && ra2 > 0.0, vb = mine2 && jl > i2 && rb2 > 0.0;
+            const double ira = rsqrt_f64(fmax(ra2, 1e-60)), irb = rsqrt_f64(fmax(rb2, 1e-60));
+            const double rpa = fmax(ra2, 1e-60) * ira * kOneOverPi, rpb = fmax(rb2, 1e-60) * irb * kOneOverPi;
+            float ca = 0.f, sa2 = 0.f, cb = 0.f, sb2 = 0.f;
+#pragma unroll 2
+            for (int m = 0; m < nqa; ++m) {
+              const double qm = qvl[m];
+              const float u = ul[m], v = vl[m];
+              const SinCosF ea = sincos_qr(qm, rpa);
+              const SinCosF eb = sincos_qr(qm, rpb);
+              ca = fmaf(u, ea.c, ca);
+              sa2 = fmaf(v, ea.s, sa2);
+              cb = fmaf(u, eb.c, cb);
+              sb2 = fmaf(v, eb.s, sb2);
+            }
+            const double GA = adj_force_direct(va, ira, ca, sa2);
+            const double GB = adj_force_direct(vb, irb, cb, sb2);
+            const double cax = GA * ax, cay = GA * ay, caz = GA * az;
+            const double cbx = GB * bx, cby = GB * by, cbz = GB * bz;
+            g1x += cax;
+            g1y += cay;
+            g1z += caz;
+            g2x += cbx;
+            g2y += cby;
+            g2z += cbz;
+            const float sx = wave_total(static_cast<float>(cax + cbx));
+            const float sy = wave_total(static_cast<float>(cay + cby));
+            const float sz = wave_total(static_cast<float>(caz + cbz));
+            if (lane == 0) {
+              double* gj = gjl + 3 * (jl - j0);
+              gj[0] -= sx;
+              gj[1] -= sy;
+              gj[2] -= sz;
+            }
+          }
+          continue;
+        }
 #pragma unroll 1
         for (int jl = sa; jl < sb; ++jl) {
           const double4 pj = sj[jl - j0];
@@ -307,8 +364,18 @@ hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st) {
   if (a.n_strips <= 0) return hipSuccess;
   const dim3 grid(static_cast<uint32_t>(a.n_strips), nchunks);
   switch (a.geo.bj) {
-    case 128: hipLaunchKernelGGL((k_adjoint<128>), grid, dim3(kWave), 0, st, a); break;
-    case 256: hipLaunchKernelGGL((k_adjoint<256>), grid, dim3(kWave), 0, st, a); break;
+    case 128:
+      if (a.qdev)
+        hipLaunchKernelGGL((k_adjoint<128, true>), grid, dim3(kWave), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_adjoint<128, false>), grid, dim3(kWave), 0, st, a);
+      break;
+    case 256:
+      if (a.qdev)
+        hipLaunchKernelGGL((k_adjoint<256, true>), grid, dim3(kWave), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_adjoint<256, false>), grid, dim3(kWave), 0, st, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -627,9 +627,14 @@ size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_
   if (check_sizes(n, t, nq, grad ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES) != SAS_OK) return 0;
   const std::vector<int64_t> sizes{n};
   if (grad) {
-    Schedule sc = make_schedule(ctx, sizes, t, nq);
-    add_adjoint(&sc, n, nq);  // the gradient needs a uniform grid and the type form
-    return make_layout(sc, t, nq).total;
+    // the type form; the recurrence or, for a non-uniform grid, the direct variants
+    size_t need = 0;
+    for (bool direct : {false, true}) {
+      Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, direct);
+      add_adjoint(&sc, n, nq);
+      need = std::max(need, make_layout(sc, t, nq).total);
+    }
+    return need;
   }
   // the grid is not known here: cover the recurrence and the direct form
   const bool pa = use_per_atom(ctx, t, n);
@@ -920,10 +925,12 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types || !grad_out)) return fail(SAS_ERR_INVALID_ARG, "coords/types/grad_out is NULL");
   if (!table || !dL_dI) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI is NULL");
-  double q0 = 0, dq = 0;
-  st = sas_q_grid_check(q, nq, &q0, &dq);
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
-  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  const double q0 = grid.q0, dq = grid.dq;
+  // a non-uniform grid takes the direct variants of the forward and the adjoint
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform);
   add_adjoint(&sc, n, nq);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
@@ -934,6 +941,8 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(workspace);
+  st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
+  if (st != SAS_OK) return st;
   if (I_out) {
     st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, q0, dq, I_out, workspace, hs);
     if (st != SAS_OK) return st;
@@ -963,6 +972,7 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   a.n_strips = sc.n_strips_adj;
   a.q0 = q0;
   a.dq = dq;
+  a.qdev = sc.direct ? reinterpret_cast<const double*>(w + L.qdev) : nullptr;
   {
     LaunchTimer timer(ctx, hs, true);
     SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));

@@ -116,10 +116,44 @@ __device__ __forceinline__ float parity_sign(double k) {
 // sin(pi (-1)^k x): the parity of k flips the sign bit of x.  sin(pi x) is
 // x * P(x^2) with P the degree-4 minimax fit of relative error 5e-9
 // (coefficients rounded to FP32, 4e-8; fit_sinpi.py beside this file
-// reproduces them).  Four FP64 and eight FP32 instructions per call.
+// reproduces them and the cosine's below).  Four FP64 and eight FP32
+// instructions per call.
 constexpr double kRoundMagic = 0x1.8p+52;
 constexpr float kSinPi0 = 0x1.921fb6p+1f, kSinPi1 = -0x1.4abbc2p+2f, kSinPi2 = 0x1.4668b0p+1f,
                 kSinPi3 = -0x1.324ccap-1f, kSinPi4 = 0x1.3daff6p-4f;
+
+constexpr float kCosPi0 = 0x1.000000p+0f, kCosPi1 = -0x1.3bd3ccp+2f, kCosPi2 = 0x1.03c1e4p+2f,
+                kCosPi3 = -0x1.55d076p+0f, kCosPi4 = 0x1.e126f2p-3f, kCosPi5 = -0x1.8fb73ep-6f;
+
+// sin(q r) and cos(q r) in FP32 for the direct adjoint, by the same reduction:
+// sin(q r) = sin(pi (-1)^k x), cos(q r) = (-1)^k cos(pi x), cos(pi x) = Q(x^2)
+// with Q the degree-5 minimax fit of absolute error 2e-10 (2e-8 with FP32
+// coefficients).
+struct SinCosF {
+  float s, c;
+};
+
+__device__ __forceinline__ SinCosF sincos_qr(double q, double rp) {
+  const double s = fma(q, rp, kRoundMagic);
+  const double k = s - kRoundMagic;
+  const float x = static_cast<float>(fma(q, rp, -k));
+  const unsigned flip = static_cast<unsigned>(__double2loint(s)) << 31;
+  const float xs = __uint_as_float(__float_as_uint(x) + flip);
+  const float y = x * x;
+  float p = fmaf(y, kSinPi4, kSinPi3);
+  p = fmaf(p, y, kSinPi2);
+  p = fmaf(p, y, kSinPi1);
+  p = fmaf(p, y, kSinPi0);
+  float c = fmaf(y, kCosPi5, kCosPi4);
+  c = fmaf(c, y, kCosPi3);
+  c = fmaf(c, y, kCosPi2);
+  c = fmaf(c, y, kCosPi1);
+  c = fmaf(c, y, kCosPi0);
+  SinCosF r;
+  r.s = xs * p;
+  r.c = __uint_as_float(__float_as_uint(c) + flip);
+  return r;
+}
 
 __device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
   const double s = fma(q, rp, kRoundMagic);

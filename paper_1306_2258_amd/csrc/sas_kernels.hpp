@@ -74,6 +74,7 @@ struct AdjArgs {
   double* gJ;           // [chunks][strips][g*bj][3] j-side partial sums
   int64_t n_strips;
   double q0, dq;
+  const double* qdev;   // non-null: arbitrary grid [Nq] on the device (direct variant)
 };
 
 // Host-side helpers implemented in sas_kernels.hip / sas_adjoint.hip.

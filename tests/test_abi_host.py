@@ -138,9 +138,10 @@ def test_binding_q_grid_check():
 
 
 def test_sine_polynomial_constants_match_their_fit():
-    """The direct form's FP32 sine coefficients in sas_device.hpp are the ones
-    the committed Remez fit produces, and they reach 5e-8 relative on
-    |x| <= 1/2 (evaluated in FP64 here)."""
+    """The direct form's FP32 sine and cosine coefficients in sas_device.hpp
+    are the ones the committed Remez fit produces, and they reach 5e-8
+    relative (sine) and 3e-8 absolute (cosine) on |x| <= 1/2 (evaluated in
+    FP64 here)."""
     import importlib.util
     import re
 
@@ -148,9 +149,17 @@ def test_sine_polynomial_constants_match_their_fit():
     spec = importlib.util.spec_from_file_location("fit_sinpi", os.path.join(root, "fit_sinpi.py"))
     fit = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(fit)
-    coef, level = fit.remez()
+    coef, level = fit.remez(fit.sin_target, 4, True)
     assert level < 1e-8
     src = open(os.path.join(root, "sas_device.hpp")).read()
+    ccoef, clevel = fit.remez(fit.cos_target, 5, False)
+    assert clevel < 1e-9
+    cfound = {int(k): float.fromhex(v) for k, v in re.findall(r"kCosPi(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
+    assert sorted(cfound) == [0, 1, 2, 3, 4, 5]
+    cc32 = np.array([cfound[k] for k in range(6)])
+    assert np.array_equal(cc32, ccoef.astype(np.float32).astype(np.float64))
+    xx = np.linspace(-0.5, 0.5, 100001)
+    assert np.max(np.abs(np.polyval(cc32[::-1], xx * xx) - np.cos(np.pi * xx))) < 3e-8
     found = {int(k): float.fromhex(v) for k, v in re.findall(r"kSinPi(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
     assert sorted(found) == [0, 1, 2, 3, 4]
     c32 = np.array([found[k] for k in range(5)])

@@ -157,3 +157,41 @@ def test_autograd_function(sd):
     ref = oracle.grad(m.coords, m.types, m.table, m.q, weights(m))
     assert x.grad.dtype == torch.float32
     assert rel_norm(x.grad.double().cpu().numpy(), ref) <= GTOL
+
+
+def test_grad_central_differences_of_gpu_profile(sd):
+    """The adjoint against central differences of the GPU's own profile
+    (chi^2 of the lattice-like workload at reduced size): for 6 atoms x 3
+    coordinates, (chi2(x + h) - chi2(x - h)) / (x+h - (x-h)) with the step
+    taken on the FP32 coordinates, h = 0.05 A (truncation and the profile's
+    1e-7-level rounding noise both stay near 1e-3 of the gradient)."""
+    import torch
+
+    say("adjoint vs central differences of the GPU profile")
+    m = W.random_molecule(2700, 400, 40, t=1, q0=0.0, q1=0.5, extent=24.0, widths=[2.0])
+    target = oracle.profile(m.coords + np.float32(0.3) * np.random.default_rng(1).normal(size=m.coords.shape)
+                            .astype(np.float32), m.types, m.table, m.q)
+    c, t, tab = dev(m)
+
+    def chi2_gpu(coords):
+        I = sd.debye_profile(torch.from_numpy(coords).cuda(), t, tab, m.q).cpu().numpy()
+        return oracle.chi2(I, target)[0]
+
+    I0 = sd.debye_profile(c, t, tab, m.q).cpu().numpy()
+    _, w = oracle.chi2(I0, target)
+    g = gpu_grad(sd, m, w)
+    atoms = np.random.default_rng(2).choice(m.n, size=6, replace=False)
+    fd, ad = [], []
+    for a in atoms:
+        for k in range(3):
+            xp = m.coords.copy()
+            xm = m.coords.copy()
+            xp[a, k] = np.float32(m.coords[a, k] + np.float32(0.05))
+            xm[a, k] = np.float32(m.coords[a, k] - np.float32(0.05))
+            step = float(xp[a, k]) - float(xm[a, k])
+            fd.append((chi2_gpu(xp) - chi2_gpu(xm)) / step)
+            ad.append(g[a, k])
+    fd, ad = np.array(fd), np.array(ad)
+    e = rel_norm(ad, fd)
+    print(f"adjoint vs central differences: rel err {e:.3e}")
+    assert e <= 1e-2

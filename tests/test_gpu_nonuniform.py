@@ -211,15 +211,66 @@ def test_nonuniform_batched_and_plan(sd):
     plan.close()
 
 
-def test_nonuniform_gradient_rejected(sd):
+GTOL = 1e-5
+
+
+def _grad_check(sd, m, w, atoms=None, with_profile=False):
     import torch
 
-    say("gradient with a non-uniform grid -> status 2")
-    m = W.random_molecule(780, 50, 0, q=W.log_grid(1e-2, 1.0, 20))
     c, t, tab = to_dev(m)
-    with pytest.raises(sd.SasError) as e:
-        sd.debye_grad(c, t, tab, m.q, torch.ones(20, dtype=torch.float64, device="cuda"))
-    assert e.value.status == 2
+    wd = torch.from_numpy(np.asarray(w, dtype=np.float64)).cuda()
+    out = sd.debye_grad(c, t, tab, m.q, wd, with_profile=with_profile)
+    g = (out[0] if with_profile else out).cpu().numpy()
+    assert np.all(np.isfinite(g))
+    ref = oracle.grad(m.coords, m.types, m.table, m.q, w, atoms=atoms)
+    got = g if atoms is None else g[atoms]
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"grad rel err {e:.3e}")
+    assert e <= GTOL, e
+    return out
+
+
+@pytest.mark.parametrize("n", [2, 3, 65, 129, 300])
+def test_nonuniform_gradient_sizes(sd, n):
+    say(f"gradient on a random grid, N={n}")
+    q = W.random_grid(780 + n, 0.0, 1.0, 37)
+    m = W.random_molecule(780 + n, n, 0, q=q, extent=3.0 * max(n, 1) ** (1 / 3) + 2.0)
+    _grad_check(sd, m, np.random.default_rng(n).normal(size=len(q)))
+
+
+@pytest.mark.parametrize("grid", ["log_150", "two_segment_70", "zero_then_log_40", "random_600"])
+def test_nonuniform_gradient_grids(sd, grid):
+    say(f"gradient on grid {grid}")
+    q = W.random_grid(790, 0.0, 1.0, 600) if grid == "random_600" else GRIDS[grid]()
+    m = W.random_molecule(791, 500, 0, t=5, q=q, extent=22.0)
+    _grad_check(sd, m, np.random.default_rng(7).normal(size=len(q)))
+
+
+def test_nonuniform_gradient_coincident_and_profile(sd):
+    import torch
+
+    say("gradient on a log grid: coincident atoms, profile output equals the plain call")
+    q = W.log_grid(2e-3, 0.9, 64)
+    m = W.random_molecule(795, 700, 0, t=3, q=q, extent=26.0)
+    m.coords[9] = m.coords[4]
+    g, I = _grad_check(sd, m, np.random.default_rng(9).normal(size=len(q)), with_profile=True)
+    assert np.array_equal(I.cpu().numpy(), gpu_profile(sd, m))
+
+
+def test_nonuniform_autograd(sd):
+    import torch
+
+    say("autograd DebyeProfile on a log grid")
+    q = W.log_grid(1e-3, 0.8, 30)
+    m = W.random_molecule(796, 300, 0, q=q, extent=15.0)
+    c, t, tab = to_dev(m)
+    x = c.clone().requires_grad_(True)
+    I = sd.DebyeProfile.apply(x, t, tab, m.q)
+    w = np.random.default_rng(3).normal(size=len(q))
+    (I * torch.from_numpy(w).cuda()).sum().backward()
+    ref = oracle.grad(m.coords, m.types, m.table, m.q, w)
+    got = x.grad.double().cpu().numpy()
+    assert float(np.linalg.norm(got - ref) / np.linalg.norm(ref)) <= GTOL
 
 
 def test_dna_rod_50k_log_grid(sd):
