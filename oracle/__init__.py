@@ -7,8 +7,9 @@ shares no code, headers or constants with it.
 ``debye_oracle.c`` is the plain definition of the Debye sum (Background
 section, Eq. 2) in FP64 with compensated sums; this module only marshals
 numpy arrays into it.  ``profile_numpy`` is a second, vectorised numpy
-transcription used for tiny inputs in tests; ``chi2`` holds the fit loss of
-the differentiation workload.
+transcription used for tiny inputs in tests; ``grad_table`` is the
+derivative of Eq. 2 with respect to the form-factor table, written out in
+numpy; ``chi2`` holds the fit loss of the differentiation workload.
 """
 from __future__ import annotations
 
@@ -120,6 +121,32 @@ def profile_numpy(coords, types, table, q):
             s = np.where(x == 0.0, 1.0, np.sin(x) / np.where(x == 0.0, 1.0, x))
         out[m] = np.sum(f[:, None] * f[None, :] * s)
     return out
+
+
+def grad_table(coords, types, table, q, w, rows: int = 512):
+    """dL/dtable[t][m] = w_m dI(q_m)/df_t(q_m), FP64 [T, Nq].
+
+    Eq. 2 is, at each q, a quadratic form in the form factors, so
+        dI(q_m)/df_t(q_m) = 2 sum_{i of type t} sum_j f_{type j}(q_m) sinc(q_m r_ij)
+    with j over all atoms including i (sinc(0) = 1); q values are independent.
+    Written out directly in numpy (blocks of ``rows`` atoms i, all j)."""
+    c, t, tab, qq = _prep(coords, types, table, q)
+    ww = np.asarray(w, dtype=np.float64).reshape(-1)
+    if ww.shape[0] != qq.shape[0]:
+        raise ValueError("w must have one weight per q")
+    n, nt = c.shape[0], tab.shape[0]
+    out = np.zeros((nt, qq.shape[0]))
+    for a0 in range(0, n, rows):
+        a1 = min(n, a0 + rows)
+        d = c[a0:a1, None, :] - c[None, :, :]
+        r = np.sqrt((d * d).sum(-1))
+        for m, qm in enumerate(qq):
+            x = qm * r
+            with np.errstate(invalid="ignore", divide="ignore"):
+                s = np.where(x == 0.0, 1.0, np.sin(x) / np.where(x == 0.0, 1.0, x))
+            phi = s @ tab[t, m]
+            out[:, m] += np.bincount(t[a0:a1], weights=phi, minlength=nt)
+    return 2.0 * ww[None, :] * out
 
 
 def chi2(I, target, rel_sigma: float = 0.01):

@@ -295,6 +295,53 @@ def test_chi2_weights_are_the_derivative():
 
 
 # ---------------------------------------------------------------------------
+# Table-gradient pins
+# ---------------------------------------------------------------------------
+
+def _table_case():
+    m = W.random_molecule(83, 11, 6, t=3, q0=0.0, q1=1.1, extent=8.0, widths=[0.4, 0.9, 1.5])
+    w = np.random.default_rng(6).normal(size=len(m.q))
+    return m.coords.astype(np.float64), m.types, m.table.astype(np.float64), m.q, w
+
+
+def test_grad_table_vs_central_differences_of_the_c_oracle():
+    """At each q Eq. 2 is quadratic in the table, so a central difference of
+    the C oracle's profile is exact up to rounding: it pins the numpy
+    derivative to an independent code path."""
+    c, t, tab, q, w = _table_case()
+    g = oracle.grad_table(c, t, tab, q, w)
+    h = 1e-3
+    num = np.zeros_like(tab)
+    for a in range(tab.shape[0]):
+        for m in range(tab.shape[1]):
+            tp = tab.copy()
+            tm = tab.copy()
+            tp[a, m] += h
+            tm[a, m] -= h
+            dI = oracle.profile(c, t, tp, q)[m] - oracle.profile(c, t, tm, q)[m]
+            num[a, m] = w[m] * dI / (2 * h)
+    assert np.max(np.abs(g - num)) <= 1e-9 * np.max(np.abs(num))
+
+
+def test_grad_table_euler_identity_and_special_cases():
+    c, t, tab, q, w = _table_case()
+    ones = np.ones(len(q))
+    g = oracle.grad_table(c, t, tab, q, ones)
+    # homogeneous of degree 2: sum_t f_t dI/df_t = 2 I
+    assert rel((tab * g).sum(axis=0), 2.0 * oracle.profile(c, t, tab, q)) < 1e-12
+    # q = 0: dI/df_t = 2 n_t sum_b n_b f_b
+    n_t = np.bincount(t, minlength=tab.shape[0]).astype(np.float64)
+    assert q[0] == 0.0
+    assert rel(g[:, 0], 2.0 * n_t * (n_t @ tab[:, 0])) < 1e-13
+    # one atom: dI/df = 2 f for its type, 0 for the others
+    g1 = oracle.grad_table(c[:1], t[:1], tab, q, ones)
+    assert rel(g1[t[0]], 2.0 * tab[t[0]]) < 1e-15
+    assert np.all(np.delete(g1, t[0], axis=0) == 0.0)
+    # the weights scale each q column
+    assert rel(oracle.grad_table(c, t, tab, q, w), g * w[None, :]) < 1e-15
+
+
+# ---------------------------------------------------------------------------
 # Mutation test: plausible mistakes planted in copies of the oracle's C source
 # (on the CPU) must each be caught by at least one pin.
 # ---------------------------------------------------------------------------
