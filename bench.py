@@ -239,6 +239,10 @@ def main(argv=None):
             result["per_atom"] = bench_per_atom(sd, W, torch, dev, ms_step)
         except Exception as exc:
             result["per_atom"] = {"error": str(exc)[:200]}
+        try:
+            result["grad_table"] = bench_grad_table(sd, torch, dev, coords, types, table, m.q, ms_step)
+        except Exception as exc:
+            result["grad_table"] = {"error": str(exc)[:200]}
 
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
@@ -346,6 +350,16 @@ def bench_per_atom(sd, W, torch, dev, ms_types):
     log(f"per-atom form (T=N=50,000): {ms:.3f} ms (pair kernel {kern_ms:.3f} ms)")
     return {"form": ctx.form(), "types": int(m.table.shape[0]), "variant": {"bj": bj, "qc": qc}, "ms": ms,
             "kernel_ms": kern_ms, "pair_q_per_s": work / (ms / 1e3), "slowdown_vs_type_form": ms / ms_types}
+
+
+def bench_grad_table(sd, torch, dev, coords, types, table, q, ms_profile):
+    """dL/dtable for the rod's 5-type table on the benchmark's grid (profile
+    returned too) against the profile alone."""
+    ctx = sd.Context(0)
+    w = torch.ones(len(q), dtype=torch.float64, device=dev)
+    ms = _time(lambda: sd.debye_grad_table(coords, types, table, q, w, with_profile=True, ctx=ctx), torch)
+    log(f"table gradient + profile {ms:.3f} ms vs profile {ms_profile:.3f} ms")
+    return {"types": int(table.shape[0]), "ms_profile_plus_table_grad": ms, "ratio": ms / ms_profile}
 
 
 def bench_grad(sd, W, torch, dev):

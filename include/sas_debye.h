@@ -72,6 +72,7 @@ typedef enum {
 /* Limits of this version. */
 #define SAS_MAX_TYPES 4096          /* T for sas_debye_grad and the type-sorted form */
 #define SAS_MAX_TABLE_TYPES (1 << 24) /* T for the profile calls (per-atom form above SAS_MAX_TYPES) */
+#define SAS_MAX_TABLE_GRAD_TYPES 64 /* T for sas_debye_grad_table                   */
 #define SAS_MAX_NQ 65536            /* Nq                                          */
 #define SAS_MAX_ATOMS 100000000LL   /* atoms per structure                         */
 
@@ -98,8 +99,9 @@ const char* sas_status_string(sas_status s);
 sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq);
 
 /* Workspace bytes needed by sas_debye_profile (grad = 0; enough for a
- * uniform or a non-uniform grid) or sas_debye_grad (grad = 1) for these
- * sizes.  Returns 0 for invalid sizes. */
+ * uniform or a non-uniform grid), sas_debye_grad (grad = 1) or
+ * sas_debye_grad_table (grad = 2) for these sizes.  Returns 0 for invalid
+ * sizes. */
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad);
 
 /*
@@ -170,6 +172,27 @@ void sas_plan_destroy(sas_plan* plan);
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,
                           int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
                           double* I_out, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Vector-Jacobian product of the profile w.r.t. the form-factor table.  At
+ * each q Eq. 2 is a quadratic form in the form factors, so
+ *     grad_table[t][m] = dL_dI[m] * dI(q_m)/df_t(q_m)
+ *                      = dL_dI[m] * 2 sum_{i of type t} sum_j f_j(q_m) sinc(q_m r_ij)
+ * (j over all atoms, i included).  It is what fitting form-factor or
+ * solvent parameters needs (chain rule through the table).  One pass of the
+ * type-sorted forward kernel that also keeps per-type sums: about the cost
+ * of a profile.
+ *   dL_dI          dev double [nq]     weights
+ *   grad_table_out dev double [t][nq]  written
+ *   I_out          dev double [nq] or NULL: if given, the profile is written too
+ * q: any increasing grid (uniform: recurrence; otherwise direct).
+ * 1 <= t <= SAS_MAX_TABLE_GRAD_TYPES (SAS_ERR_UNSUPPORTED otherwise).
+ * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 2).
+ */
+sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                const float* table, int32_t t, const double* q, int32_t nq, const double* dL_dI,
+                                double* grad_table_out, double* I_out, void* workspace, size_t ws_bytes,
+                                void* stream);
 
 /*
  * Tuning controls (optional).  sas_set_variant forces the forward tile shape

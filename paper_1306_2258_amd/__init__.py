@@ -32,7 +32,7 @@ from . import _lib
 from ._lib import SasError, check, load
 
 __all__ = [
-    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched", "debye_grad",
+    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched", "debye_grad", "debye_grad_table",
     "BatchedPlan", "DebyeProfile", "debye_profile_autograd", "default_context",
 ]
 
@@ -128,8 +128,9 @@ class Context:
         return {"forward_ms": f_ms.value, "forward_launches": f_n.value, "adjoint_ms": a_ms.value,
                 "adjoint_launches": a_n.value}
 
-    def workspace_size(self, n: int, t: int, nq: int, grad: bool = False) -> int:
-        return int(load().sas_debye_workspace_size(self._h, int(n), int(t), int(nq), int(bool(grad))))
+    def workspace_size(self, n: int, t: int, nq: int, grad: int = 0) -> int:
+        """Bytes for a profile (grad 0), coordinate gradient (1) or table gradient (2)."""
+        return int(load().sas_debye_workspace_size(self._h, int(n), int(t), int(nq), int(grad)))
 
     def close(self) -> None:
         if self._h:
@@ -281,23 +282,49 @@ def debye_grad(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q
     return (grad, prof) if with_profile else grad
 
 
+def debye_grad_table(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, dL_dI: torch.Tensor, *,
+                     with_profile: bool = False, ctx: Optional[Context] = None):
+    """dL_dI[m] dI(q_m)/dtable[t][m] as float64 [T, Nq] (and the profile if
+    ``with_profile``); T <= 64."""
+    _check_inputs(coords, types, table)
+    ctx = ctx or default_context(coords.device)
+    qh = _q_host(q)
+    n, t, nq = coords.shape[0], table.shape[0], len(qh)
+    w = dL_dI.detach().to(device=coords.device, dtype=torch.float64).contiguous()
+    if w.numel() != nq:
+        raise ValueError("dL_dI needs one value per q")
+    gt = torch.empty((t, nq), dtype=torch.float64, device=coords.device)
+    prof = torch.empty(nq, dtype=torch.float64, device=coords.device) if with_profile else None
+    nbytes = ctx.workspace_size(n, t, nq, 2)
+    ws = ctx.workspace(nbytes)
+    check(load().sas_debye_grad_table(ctx.handle, _ptr(coords), _ptr(types), n, _ptr(table), t,
+                                      qh.ctypes.data_as(ctypes.c_void_p), nq, _ptr(w), _ptr(gt), _ptr(prof),
+                                      _ptr(ws), ws.numel(), _stream(coords.device)), "sas_debye_grad_table")
+    return (gt, prof) if with_profile else gt
+
+
 class DebyeProfile(torch.autograd.Function):
     """I(q) = DebyeProfile.apply(coords, types, table, q): differentiable with
-    respect to ``coords`` (float32 [N, 3]); the backward pass runs the
-    library's adjoint kernel (sas_debye_grad)."""
+    respect to ``coords`` (float32 [N, 3]) through the library's adjoint
+    kernel (sas_debye_grad) and with respect to ``table`` (float32 [T, Nq],
+    T <= 64) through sas_debye_grad_table."""
 
     @staticmethod
     def forward(ctx_, coords, types, table, q):
         qh = _q_host(q)
         ctx_.save_for_backward(coords, types, table)
         ctx_.qh = qh
-        return debye_profile(coords.detach(), types, table, qh)
+        return debye_profile(coords.detach(), types, table.detach(), qh)
 
     @staticmethod
     def backward(ctx_, grad_I):
         coords, types, table = ctx_.saved_tensors
-        g = debye_grad(coords.detach(), types, table, ctx_.qh, grad_I)
-        return g.to(coords.dtype), None, None, None
+        gc = gt = None
+        if ctx_.needs_input_grad[0]:
+            gc = debye_grad(coords.detach(), types, table.detach(), ctx_.qh, grad_I).to(coords.dtype)
+        if ctx_.needs_input_grad[2]:
+            gt = debye_grad_table(coords.detach(), types, table.detach(), ctx_.qh, grad_I).to(table.dtype)
+        return gc, None, gt, None
 
 
 def debye_profile_autograd(coords, types, table, q):

@@ -43,6 +43,7 @@ SIGNATURES = {
     "sas_plan_execute": (ctypes.c_int, [P, P]),
     "sas_plan_destroy": (None, [P]),
     "sas_debye_grad": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, P, P, P, P, SZ, P]),
+    "sas_debye_grad_table": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, P, P, P, P, SZ, P]),
     "sas_set_variant": (ctypes.c_int, [P, I32, I32]),
     "sas_get_variant": (ctypes.c_int, [P, P, P]),
     "sas_set_form": (ctypes.c_int, [P, ctypes.c_int]),

@@ -120,6 +120,7 @@ struct Schedule {
   Geometry geo{};
   bool direct = false;    // arbitrary q grid: per-q evaluation instead of the recurrence
   bool per_atom = false;  // f_j inside the pair loop, no type sort
+  int32_t tg_types = 0;   // > 0: the forward also writes per-type table-gradient rows
   int32_t qc = 0, qc_template = 0;
   int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
   // adjoint (gradient) schedule, single structure only
@@ -137,6 +138,7 @@ struct Layout {
   size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, tabp = 0, partial = 0, slices = 0;
   size_t gI = 0, gJ = 0, total = 0;
   size_t asum = 0;  // per-atom form: per pack block sums of f and f^2
+  size_t gpart = 0, gslices = 0;  // table gradient: [strips][T][Nq], [slices][T][Nq]
   // host-written block, uploaded in one copy: structure descriptors (S > 1)
   // followed by the q grid (direct form)
   size_t upload = 0, upload_bytes = 0, desc = 0, qdev = 0;
@@ -189,10 +191,12 @@ int32_t default_bj(int64_t max_n) {
 
 // Build the schedule for structure sizes `sizes` (caller order).
 Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
-                       int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false, bool per_atom = false) {
+                       int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false, bool per_atom = false,
+                       int32_t tg_types = 0) {
   Schedule sc;
   sc.direct = direct;
   sc.per_atom = per_atom;
+  sc.tg_types = tg_types;
   sc.S = static_cast<int32_t>(sizes.size());
   int64_t max_n = 0;
   for (int64_t n : sizes) {
@@ -234,12 +238,13 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   sc.geo.bj = bj;
   sc.geo.ib = sas::kWave;
   sc.geo.c = bj / sas::kWave;
-  // strips of g J blocks: g = 1 unless the partial rows would exceed 256 MiB
+  // strips of g J blocks: g = 1 unless the partial rows (with the table
+  // gradient's T rows per strip) would exceed 256 MiB
   for (int32_t g = 1;; g *= 2) {
     sc.geo.g = g;
     int64_t strips = 0;
     for (int64_t n : sizes) strips += sas::strips_of(n, sc.geo);
-    if (static_cast<double>(strips) * Nq * 8.0 <= 256.0 * 1024 * 1024 || g >= 1024) break;
+    if (static_cast<double>(strips) * Nq * 8.0 * (1 + tg_types) <= 256.0 * 1024 * 1024 || g >= 1024) break;
   }
   // execution order: largest structure first (longest-processing-time order)
   std::vector<int32_t> order(sc.S);
@@ -341,6 +346,10 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   L.tabp = take(sizeof(float) * static_cast<size_t>(T) * sc.ldt);
   L.partial = take(sizeof(double) * sc.n_strips * Nq);
   L.slices = take(sizeof(double) * sc.n_slices * Nq);
+  if (sc.tg_types > 0) {
+    L.gpart = take(sizeof(double) * sc.n_strips * static_cast<size_t>(sc.tg_types) * Nq);
+    L.gslices = take(sizeof(double) * sc.n_slices * static_cast<size_t>(sc.tg_types) * Nq);
+  }
   if (sc.grad) {
     const size_t rows = static_cast<size_t>(sc.nchunks_adj) * sc.n_strips_adj;
     L.gI = take(sizeof(double) * 3 * rows * sc.geo_adj.ib);
@@ -474,15 +483,19 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   a.q0 = q0;
   a.dq = dq;
   a.qdev = qdev;
+  a.gpart = sc.tg_types > 0 ? reinterpret_cast<double*>(w + L.gpart) : nullptr;
   {
     LaunchTimer timer(ctx, st, false);
     if (sc.per_atom)
       SAS_HIP(sas::launch_forward_pa(a, sc.n_strips, sc.qc_template, st));
+    else if (sc.tg_types > 0)
+      SAS_HIP(sas::launch_forward_tg(a, sc.n_strips, sc.qc_template, st));
     else
       SAS_HIP(sas::launch_forward(a, sc.n_strips, sc.qc_template, st));
   }
-  SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, sc.per_atom ? nullptr : toff, asum, table, T, Nq,
-                             q0, dq, qdev, I_out, st));
+  if (I_out)
+    SAS_HIP(sas::launch_reduce(sd, sc.S, sc.n_slices, partial, slices, sc.per_atom ? nullptr : toff, asum, table, T,
+                               Nq, q0, dq, qdev, I_out, st));
   return SAS_OK;
 }
 
@@ -624,8 +637,15 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 }
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
-  if (check_sizes(n, t, nq, grad ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES) != SAS_OK) return 0;
+  const int32_t max_t = grad == 2 ? SAS_MAX_TABLE_GRAD_TYPES : (grad ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES);
+  if (check_sizes(n, t, nq, max_t) != SAS_OK) return 0;
   const std::vector<int64_t> sizes{n};
+  if (grad == 2) {
+    size_t need = 0;
+    for (bool direct : {false, true})
+      need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, direct, false, t), t, nq).total);
+    return need;
+  }
   if (grad) {
     // the type form; the recurrence or, for a non-uniform grid, the direct variants
     size_t need = 0;
@@ -915,6 +935,40 @@ void sas_plan_destroy(sas_plan* p) {
     if (p->cap) (void)hipStreamDestroy(p->cap);
   }
   delete p;
+}
+
+sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                const float* table, int32_t t, const double* q, int32_t nq, const double* dL_dI,
+                                double* grad_table_out, double* I_out, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TABLE_GRAD_TYPES);
+  if (st != SAS_OK) return st;
+  if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || !dL_dI || !grad_table_out) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI/grad_table_out is NULL");
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
+  if (st != SAS_OK) return st;
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform, false, t);
+  const Layout L = make_layout(sc, t, nq);
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+  st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
+  if (st != SAS_OK) return st;
+  st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
+  if (st != SAS_OK) return st;
+  const double* qdev = sc.direct ? reinterpret_cast<const double*>(w + L.qdev) : nullptr;
+  auto* gslices = reinterpret_cast<double*>(w + L.gslices);
+  SAS_HIP(sas::launch_reduce_slices(view_of(sc, workspace, L), sc.n_slices, reinterpret_cast<const double*>(w + L.gpart),
+                                    t * nq, gslices, hs));
+  SAS_HIP(sas::launch_table_grad_final(sc.n_slices, gslices, reinterpret_cast<const int32_t*>(w + L.toff), table, t, nq,
+                                       grid.q0, grid.dq, qdev, dL_dI, grad_table_out, hs));
+  return SAS_OK;
 }
 
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,

@@ -1,0 +1,228 @@
+// The forward pair kernel of the type-segment form, as a template shared by
+// the profile (TG = false, sas_kernels.hip) and the table gradient (TG = true,
+// sas_tablegrad.hip).
+//
+// One 64-lane wave per (I block, strip of J blocks, q chunk): each lane owns
+// one i atom, the J block is staged in LDS and swept by all lanes; per pair a
+// sin/cos set-up in FP64, then the FP32 recurrence over the q chunk (or, in
+// the direct form, one sine per q); per type segment a reduction over the 64
+// lanes and an FP64 product with the segment's form factor; one FP64 partial
+// row per strip.  With TG the same strip also writes, per type, the sums that
+// the derivative of Eq. 2 with respect to the table needs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "sas_device.hpp"
+#include "sas_forward.hpp"
+#include "sas_kernels.hpp"
+#include "sas_schedule.hpp"
+
+namespace sas {
+
+template <int QC, int BJ, bool DIRECT, bool TG>
+__global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2 : 3)) void k_forward(ForwardArgs a) {
+  constexpr int NG = QC / kWave;          // full groups of 64 q values
+  constexpr int R = QC % kWave;           // values in the tail group
+  constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
+  __shared__ double4 sj[BJ];
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const int s = find_struct_by_strip(a.sd, t);
+  const StructDesc d = a.sd.get(s);
+  const StripPos sp = decode_strip(t - d.strip_off, d.n, a.geo);
+  const int n = d.n;
+  const int i = sp.I * kWave + lane;  // local sorted row of this lane's atom
+  const bool vi = i < n;
+  const int ic = vi ? i : n - 1;
+  const double4 pi = a.xyz[d.atom_off + ic];
+  const int ta = clamp_type(a.tsort[d.atom_off + ic], a.T);
+
+  const int m0 = blockIdx.y * a.qc;
+  const int nqc = min(a.qc, a.Nq - m0);   // <= QC; steps beyond nqc are computed and dropped
+  // (the padded table tabp has ldt >= m0 + QC columns, zero beyond Nq, so no
+  // per-step bounds test is needed)
+  const double qs = a.q0 + m0 * a.dq;
+  const double dq = a.dq;
+  const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
+  const int32_t* toff = a.toff + static_cast<int64_t>(s) * (a.T + 1);
+
+  // table gradient (TG): this strip's rows [T][Nq] of the sums f_b v by lane
+  // type and f_a v by segment type, zeroed by the lanes that later add to
+  // them; the I block is "pure" when every valid lane holds one type
+  double* grows = nullptr;
+  int ta0 = ta;
+  bool pure = true;
+  if constexpr (TG) {
+    grows = a.gpart + t * static_cast<int64_t>(a.T) * a.Nq + m0;
+    for (int r = 0; r < a.T; ++r)
+      for (int m = lane; m < nqc; m += kWave) grows[static_cast<int64_t>(r) * a.Nq + m] = 0.0;
+    ta0 = __shfl(ta, 0, kWave);
+    pure = __ballot(vi && ta != ta0) == 0;
+  }
+
+  // FP64 strip totals, lane-major in LDS (kept out of VGPRs: the q
+  // accumulators need nearly all of them)
+  __shared__ double tot[NT][kWave];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
+  // direct form: this chunk's q values (0 past the end of the grid)
+  __shared__ double qv[DIRECT ? QC : 1];
+  if constexpr (DIRECT) {
+    for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
+  }
+
+#pragma unroll 1
+  for (int J = sp.Ja; J < sp.Jb; ++J) {
+    const int j0 = J * BJ;
+    const int j1 = min(n, j0 + BJ);
+    __syncthreads();
+    for (int k = lane; k < j1 - j0; k += kWave) sj[k] = a.xyz[d.atom_off + j0 + k];
+    __syncthreads();
+    // first type segment that ends after j0 (toff holds absolute rows)
+    const int64_t aj0 = d.atom_off + j0, aj1 = d.atom_off + j1;
+    int lo = 0, hi = a.T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (toff[mid + 1] > aj0)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+#pragma unroll 1
+    for (int tb = lo; tb < a.T && toff[tb] < aj1; ++tb) {
+      const int sa = static_cast<int>(max(static_cast<int64_t>(toff[tb]), aj0) - d.atom_off);
+      const int sb = static_cast<int>(min(static_cast<int64_t>(toff[tb + 1]), aj1) - d.atom_off);
+      if (sa >= sb) continue;
+      // TG on a block at a type boundary: one pass over the segment per lane
+      // type present, the other lanes masked, so that each pass's lane sums
+      // belong to one type (such blocks are at most T - 1 of a structure's)
+      uint64_t rem = TG && !pure ? static_cast<uint64_t>(__ballot(vi)) : 0;
+      int at = ta0;
+      bool on = vi;
+#pragma unroll 1
+      do {
+      if constexpr (TG) {
+        if (!pure) {
+          at = __shfl(ta, __ffsll(static_cast<unsigned long long>(rem)) - 1, kWave);
+          on = vi && ta == at;
+          rem &= ~static_cast<uint64_t>(__ballot(on));
+        }
+      }
+      float acc[QC];
+#pragma unroll
+      for (int m = 0; m < QC; ++m) acc[m] = 0.f;
+      if constexpr (DIRECT) {
+        // arbitrary q grid: sin(q_m r)/r evaluated for every q, one pair per
+        // iteration (the q steps are independent of each other)
+#pragma unroll 1
+        for (int jl = sa; jl < sb; ++jl) {
+          // (the q values are re-read from LDS for every pair rather than
+          // held in 64 VGPRs: four waves per SIMD instead of three)
+          asm volatile("" ::: "memory");
+          const double4 pj = sj[jl - j0];
+          const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+          const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
+          const double ir = rsqrt_f64(r2);
+          const double rp = r2 * ir * kOneOverPi;
+          const float w = (on && jl > i) ? static_cast<float>(ir) : 0.f;
+#pragma unroll
+          for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w, acc[m]);
+        }
+      } else {
+      // two atom pairs (j, j+1) per iteration: two independent recurrence
+      // chains give the scheduler work to issue while either waits on its
+      // previous result; an odd segment ends with a masked partner
+#pragma unroll 1
+      for (int jl = sa; jl < sb; jl += 2) {
+        const int jb = jl + 1 < sb ? jl + 1 : jl;
+        // (empty volatile asm: a scheduling boundary, so the two FP64 set-ups
+        // run one after the other and their temporaries never coexist with
+        // each other and the QC accumulators)
+        const PairSeed A = pair_seed(pi, sj[jl - j0], on && jl > i, dq, qs);
+        asm volatile("" ::: "memory");
+        const PairSeed B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
+        asm volatile("" ::: "memory");
+        float za = A.z, da = A.d, zb = B.z, db = B.d;
+#pragma unroll
+        for (int m = 0; m < QC; ++m) {
+          if (m & 1) {
+            acc[m] = fmaf(A.sg, za, acc[m]);
+            acc[m] = fmaf(B.sg, zb, acc[m]);
+          } else {
+            acc[m] += za;
+            acc[m] += zb;
+          }
+          za += da;
+          zb += db;
+          da = fmaf(A.nlam, za, da);
+          db = fmaf(B.nlam, zb, db);
+        }
+      }
+      }
+      const float* fb_row = a.tabp + static_cast<int64_t>(tb) * a.ldt + m0;
+      if constexpr (TG) {
+        // lane sums v of the raw accumulators per lane type a give the
+        // profile term f_a f_b v and the table-gradient terms f_b v (row a)
+        // and f_a v (row b), all in FP64
+        double* gb = grows + static_cast<int64_t>(tb) * a.Nq;
+        auto add = [&](int g, float v, const float* fa_t, double* ga) {
+          const int m = g * kWave + lane;
+          const double fa = m < QC ? static_cast<double>(fa_t[m]) : 0.0;
+          const double fb = m < QC ? static_cast<double>(fb_row[m]) : 0.0;
+          const double vv = static_cast<double>(v);
+          tot[g][lane] = fma(fa * fb, vv, tot[g][lane]);
+          if (m < nqc) {
+            ga[m] = fma(fb, vv, ga[m]);
+            gb[m] = fma(fa, vv, gb[m]);
+          }
+        };
+        // every contributing lane holds type `at` (this pass's type)
+        const float* fat = a.tabp + static_cast<int64_t>(at) * a.ldt + m0;
+        asm volatile("" : "+v"(fat));
+        double* ga = grows + static_cast<int64_t>(at) * a.Nq;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) add(g, lane_transpose_reduce64(acc + g * kWave, lane), fat, ga);
+        if constexpr (R > 0) add(NG, lane_allreduce_tail<R>(acc + NG * kWave, lane), fat, ga);
+      } else {
+      // weight by this lane's f_a(q_m), sum over lanes, weight by f_b(q_m) in FP64
+      // (the row pointer is laundered so that the loads stay here instead of
+      // being hoisted out of the j loops, where they would pin QC registers)
+      const float* far = fa_row;
+      asm volatile("" : "+v"(far));
+#pragma unroll
+      for (int m = 0; m < QC; ++m) acc[m] *= far[m];
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const float v = lane_transpose_reduce64(acc + g * kWave, lane);
+        tot[g][lane] = fma(static_cast<double>(v), static_cast<double>(fb_row[g * kWave + lane]), tot[g][lane]);
+      }
+      if constexpr (R > 0) {
+        const float v = lane_allreduce_tail<R>(acc + NG * kWave, lane);
+        const float fb = lane < R ? fb_row[NG * kWave + lane] : 0.f;
+        tot[NG][lane] = fma(static_cast<double>(v), static_cast<double>(fb), tot[NG][lane]);
+      }
+      }
+      } while (TG && rem);
+    }
+  }
+  double* out = a.partial + t * a.Nq + m0;
+#pragma unroll
+  for (int g = 0; g < NT; ++g) {
+    const int m = g * kWave + lane;
+    if (m < nqc) out[m] = tot[g][lane];
+  }
+}
+
+template <int QC, bool DIRECT, bool TG>
+hipError_t launch_forward_qc(const ForwardArgs& a, dim3 grid, hipStream_t st) {
+  switch (a.geo.bj) {
+    case 64: hipLaunchKernelGGL((k_forward<QC, 64, DIRECT, TG>), grid, dim3(kWave), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_forward<QC, 128, DIRECT, TG>), grid, dim3(kWave), 0, st, a); break;
+    case 256: hipLaunchKernelGGL((k_forward<QC, 256, DIRECT, TG>), grid, dim3(kWave), 0, st, a); break;
+    case 512: hipLaunchKernelGGL((k_forward<QC, 512, DIRECT, TG>), grid, dim3(kWave), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sas

@@ -8,7 +8,8 @@
 //   pack     stable counting sort of each structure's atoms by type, FP64
 //            coordinates in the sorted order (so that every J block splits into
 //            a few constant-type segments and f_a f_b factors out of the sum);
-//   forward  one 64-lane wave per (I block, strip of J blocks, q chunk): each
+//   forward  (template in sas_forward_kernel.hpp) one 64-lane wave per
+//            (I block, strip of J blocks, q chunk): each
 //            lane owns one i atom, the J block is staged in LDS and swept by
 //            all lanes; per pair a sin/cos set-up in FP64, then an FP32
 //            second-order recurrence over the uniform q grid; per type segment
@@ -20,6 +21,7 @@
 
 #include "sas_device.hpp"
 #include "sas_forward.hpp"
+#include "sas_forward_kernel.hpp"
 #include "sas_kernels.hpp"
 #include "sas_schedule.hpp"
 
@@ -153,161 +155,10 @@ hipError_t launch_pack(const float* coords, const int32_t* types, const DescView
 // Forward strips (recurrence and lane reductions: sas_forward.hpp).
 // ---------------------------------------------------------------------------
 
-template <int QC, int BJ, bool DIRECT>
-__global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2 : 3)) void k_forward(ForwardArgs a) {
-  constexpr int NG = QC / kWave;          // full groups of 64 q values
-  constexpr int R = QC % kWave;           // values in the tail group
-  constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
-  __shared__ double4 sj[BJ];
-  const int lane = threadIdx.x;
-  const int64_t t = blockIdx.x;
-  const int s = find_struct_by_strip(a.sd, t);
-  const StructDesc d = a.sd.get(s);
-  const StripPos sp = decode_strip(t - d.strip_off, d.n, a.geo);
-  const int n = d.n;
-  const int i = sp.I * kWave + lane;  // local sorted row of this lane's atom
-  const bool vi = i < n;
-  const int ic = vi ? i : n - 1;
-  const double4 pi = a.xyz[d.atom_off + ic];
-  const int ta = clamp_type(a.tsort[d.atom_off + ic], a.T);
-
-  const int m0 = blockIdx.y * a.qc;
-  const int nqc = min(a.qc, a.Nq - m0);   // <= QC; steps beyond nqc are computed and dropped
-  // (the padded table tabp has ldt >= m0 + QC columns, zero beyond Nq, so no
-  // per-step bounds test is needed)
-  const double qs = a.q0 + m0 * a.dq;
-  const double dq = a.dq;
-  const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
-  const int32_t* toff = a.toff + static_cast<int64_t>(s) * (a.T + 1);
-
-  // FP64 strip totals, lane-major in LDS (kept out of VGPRs: the q
-  // accumulators need nearly all of them)
-  __shared__ double tot[NT][kWave];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
-  // direct form: this chunk's q values (0 past the end of the grid)
-  __shared__ double qv[DIRECT ? QC : 1];
-  if constexpr (DIRECT) {
-    for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
-  }
-
-#pragma unroll 1
-  for (int J = sp.Ja; J < sp.Jb; ++J) {
-    const int j0 = J * BJ;
-    const int j1 = min(n, j0 + BJ);
-    __syncthreads();
-    for (int k = lane; k < j1 - j0; k += kWave) sj[k] = a.xyz[d.atom_off + j0 + k];
-    __syncthreads();
-    // first type segment that ends after j0 (toff holds absolute rows)
-    const int64_t aj0 = d.atom_off + j0, aj1 = d.atom_off + j1;
-    int lo = 0, hi = a.T - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (toff[mid + 1] > aj0)
-        hi = mid;
-      else
-        lo = mid + 1;
-    }
-#pragma unroll 1
-    for (int tb = lo; tb < a.T && toff[tb] < aj1; ++tb) {
-      const int sa = static_cast<int>(max(static_cast<int64_t>(toff[tb]), aj0) - d.atom_off);
-      const int sb = static_cast<int>(min(static_cast<int64_t>(toff[tb + 1]), aj1) - d.atom_off);
-      if (sa >= sb) continue;
-      float acc[QC];
-#pragma unroll
-      for (int m = 0; m < QC; ++m) acc[m] = 0.f;
-      if constexpr (DIRECT) {
-        // arbitrary q grid: sin(q_m r)/r evaluated for every q, one pair per
-        // iteration (the q steps are independent of each other)
-#pragma unroll 1
-        for (int jl = sa; jl < sb; ++jl) {
-          // (the q values are re-read from LDS for every pair rather than
-          // held in 64 VGPRs: four waves per SIMD instead of three)
-          asm volatile("" ::: "memory");
-          const double4 pj = sj[jl - j0];
-          const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
-          const double ir = rsqrt_f64(r2);
-          const double rp = r2 * ir * kOneOverPi;
-          const float w = (vi && jl > i) ? static_cast<float>(ir) : 0.f;
-#pragma unroll
-          for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w, acc[m]);
-        }
-      } else {
-      // two atom pairs (j, j+1) per iteration: two independent recurrence
-      // chains give the scheduler work to issue while either waits on its
-      // previous result; an odd segment ends with a masked partner
-#pragma unroll 1
-      for (int jl = sa; jl < sb; jl += 2) {
-        const int jb = jl + 1 < sb ? jl + 1 : jl;
-        // (empty volatile asm: a scheduling boundary, so the two FP64 set-ups
-        // run one after the other and their temporaries never coexist with
-        // each other and the QC accumulators)
-        const PairSeed A = pair_seed(pi, sj[jl - j0], vi && jl > i, dq, qs);
-        asm volatile("" ::: "memory");
-        const PairSeed B = pair_seed(pi, sj[jb - j0], vi && jb > i && jl + 1 < sb, dq, qs);
-        asm volatile("" ::: "memory");
-        float za = A.z, da = A.d, zb = B.z, db = B.d;
-#pragma unroll
-        for (int m = 0; m < QC; ++m) {
-          if (m & 1) {
-            acc[m] = fmaf(A.sg, za, acc[m]);
-            acc[m] = fmaf(B.sg, zb, acc[m]);
-          } else {
-            acc[m] += za;
-            acc[m] += zb;
-          }
-          za += da;
-          zb += db;
-          da = fmaf(A.nlam, za, da);
-          db = fmaf(B.nlam, zb, db);
-        }
-      }
-      }
-      // weight by this lane's f_a(q_m), sum over lanes, weight by f_b(q_m) in FP64
-      // (the row pointer is laundered so that the loads stay here instead of
-      // being hoisted out of the j loops, where they would pin QC registers)
-      const float* far = fa_row;
-      asm volatile("" : "+v"(far));
-#pragma unroll
-      for (int m = 0; m < QC; ++m) acc[m] *= far[m];
-      const float* fb_row = a.tabp + static_cast<int64_t>(tb) * a.ldt + m0;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const float v = lane_transpose_reduce64(acc + g * kWave, lane);
-        tot[g][lane] = fma(static_cast<double>(v), static_cast<double>(fb_row[g * kWave + lane]), tot[g][lane]);
-      }
-      if constexpr (R > 0) {
-        const float v = lane_allreduce_tail<R>(acc + NG * kWave, lane);
-        const float fb = lane < R ? fb_row[NG * kWave + lane] : 0.f;
-        tot[NG][lane] = fma(static_cast<double>(v), static_cast<double>(fb), tot[NG][lane]);
-      }
-    }
-  }
-  double* out = a.partial + t * a.Nq + m0;
-#pragma unroll
-  for (int g = 0; g < NT; ++g) {
-    const int m = g * kWave + lane;
-    if (m < nqc) out[m] = tot[g][lane];
-  }
-}
-
 bool forward_qc_supported(int32_t qc) {
   return qc == 16 || qc == 32 || qc == 50 || qc == 64 || qc == 100 || qc == 128 || qc == 150 || qc == 200;
 }
 bool forward_bj_supported(int32_t bj) { return bj == 64 || bj == 128 || bj == 256 || bj == 512; }
-
-template <int QC, bool DIRECT>
-static hipError_t launch_forward_qc(const ForwardArgs& a, dim3 grid, hipStream_t st) {
-  switch (a.geo.bj) {
-    case 64: hipLaunchKernelGGL((k_forward<QC, 64, DIRECT>), grid, dim3(kWave), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_forward<QC, 128, DIRECT>), grid, dim3(kWave), 0, st, a); break;
-    case 256: hipLaunchKernelGGL((k_forward<QC, 256, DIRECT>), grid, dim3(kWave), 0, st, a); break;
-    case 512: hipLaunchKernelGGL((k_forward<QC, 512, DIRECT>), grid, dim3(kWave), 0, st, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
 
 bool direct_qc_supported(int32_t qc) { return qc == 32; }
 
@@ -317,19 +168,19 @@ hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t 
   const dim3 grid(static_cast<uint32_t>(n_strips_total), nchunks);
   if (a.qdev) {
     switch (qc_template) {
-      case 32: return launch_forward_qc<32, true>(a, grid, st);
+      case 32: return launch_forward_qc<32, true, false>(a, grid, st);
       default: return hipErrorInvalidValue;
     }
   }
   switch (qc_template) {
-    case 16: return launch_forward_qc<16, false>(a, grid, st);
-    case 32: return launch_forward_qc<32, false>(a, grid, st);
-    case 50: return launch_forward_qc<50, false>(a, grid, st);
-    case 64: return launch_forward_qc<64, false>(a, grid, st);
-    case 100: return launch_forward_qc<100, false>(a, grid, st);
-    case 128: return launch_forward_qc<128, false>(a, grid, st);
-    case 150: return launch_forward_qc<150, false>(a, grid, st);
-    case 200: return launch_forward_qc<200, false>(a, grid, st);
+    case 16: return launch_forward_qc<16, false, false>(a, grid, st);
+    case 32: return launch_forward_qc<32, false, false>(a, grid, st);
+    case 50: return launch_forward_qc<50, false, false>(a, grid, st);
+    case 64: return launch_forward_qc<64, false, false>(a, grid, st);
+    case 100: return launch_forward_qc<100, false, false>(a, grid, st);
+    case 128: return launch_forward_qc<128, false, false>(a, grid, st);
+    case 150: return launch_forward_qc<150, false, false>(a, grid, st);
+    case 200: return launch_forward_qc<200, false, false>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -390,6 +241,15 @@ __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double*
     }
     I_out[static_cast<int64_t>(d.orig) * Nq + m] = val;
   }
+}
+
+hipError_t launch_reduce_slices(const DescView& sd, int64_t n_slices_total, const double* partial, int32_t row,
+                                double* slice_sums, hipStream_t st) {
+  if (n_slices_total > 0) {
+    hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total)), dim3(256), 0, st, sd, partial,
+                       row, slice_sums);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,

@@ -55,6 +55,7 @@ struct ForwardArgs {
   int32_t qc;           // q values per chunk (grid.y = number of chunks)
   double q0, dq;        // uniform grid q_m = q0 + m dq (recurrence form)
   const double* qdev;   // non-null: arbitrary grid [Nq] on the device (direct form)
+  double* gpart;        // table gradient only: [strips][T][Nq] per-type sums
 };
 
 constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
@@ -92,6 +93,17 @@ hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t 
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
                          double* slice_sums, const int32_t* toff, const double* asum, const float* table, int32_t T,
                          int32_t Nq, double q0, double dq, const double* qdev, double* I_out, hipStream_t st);
+
+// Sum rows of `row` values over each slice of kSliceTiles strips, in order.
+hipError_t launch_reduce_slices(const DescView& sd, int64_t n_slices_total, const double* partial, int32_t row,
+                                double* slice_sums, hipStream_t st);
+
+// Table gradient (sas_tablegrad.hip): the forward pass that also writes the
+// per-type sums, and the final step that forms w_m dI/df_t(q_m).
+hipError_t launch_forward_tg(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
+hipError_t launch_table_grad_final(int64_t n_slices, const double* gslices, const int32_t* toff,
+                                   const float* table, int32_t T, int32_t Nq, double q0, double dq, const double* qdev,
+                                   const double* w, double* grad_table, hipStream_t st);
 
 // Per-atom form (sas_peratom.hip).
 hipError_t launch_pack_plain(const float* coords, const int32_t* types, int64_t n_total, int32_t T, double4* xyz,
