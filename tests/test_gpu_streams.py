@@ -1,0 +1,98 @@
+"""Streams and graphs at the boundary: calls on separate non-default streams
+overlap and give the serial results bitwise; a plain profile call captured
+by the caller into a hipGraph (torch.cuda.graph) replays correctly with the
+caller's own eager work between replays."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_2258_amd as mod
+
+    return mod
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(m):
+    import torch
+
+    return (torch.from_numpy(m.coords).cuda(), torch.from_numpy(m.types).cuda(), torch.from_numpy(m.table).cuda())
+
+
+def test_two_streams_two_contexts(sd):
+    import torch
+
+    say("two profiles on two non-default streams")
+    ma = W.random_molecule(1600, 3000, 80, q0=0.0, q1=1.0, extent=40.0)
+    mb = W.random_molecule(1601, 2500, 0, q=W.log_grid(1e-3, 1.0, 60), extent=35.0)
+    ca, ta, fa = to_dev(ma)
+    cb, tb, fb = to_dev(mb)
+    ctx_a, ctx_b = sd.Context(0), sd.Context(0)
+    serial_a = sd.debye_profile(ca, ta, fa, ma.q, ctx=ctx_a).clone()
+    serial_b = sd.debye_profile(cb, tb, fb, mb.q, ctx=ctx_b).clone()
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            oa = sd.debye_profile(ca, ta, fa, ma.q, ctx=ctx_a)
+        with torch.cuda.stream(s2):
+            ob = sd.debye_profile(cb, tb, fb, mb.q, ctx=ctx_b)
+        outs.append((oa, ob))
+    torch.cuda.synchronize()
+    for oa, ob in outs:
+        assert torch.equal(oa, serial_a)
+        assert torch.equal(ob, serial_b)
+    ref = oracle.profile(ma.coords, ma.types, ma.table, ma.q)
+    assert np.max(np.abs(serial_a.cpu().numpy() - ref) / ref) <= 1e-6
+
+
+def test_plain_call_captured_in_caller_graph(sd):
+    import torch
+
+    say("plain profile captured by torch.cuda.graph, 3 replays with eager work between")
+    m = W.random_molecule(1610, 2000, 100, q0=0.0, q1=1.0, extent=36.0)
+    c, t, tab = to_dev(m)
+    ctx = sd.Context(0)
+    out = torch.empty(len(m.q), dtype=torch.float64, device="cuda")
+    eager = sd.debye_profile(c, t, tab, m.q, ctx=ctx).clone()  # warms the context's workspace
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sd.debye_profile(c, t, tab, m.q, ctx=ctx, out=out)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for rep in range(3):
+        # change the coordinates in place, run an eager profile, then replay
+        c.add_(torch.from_numpy(rng.normal(scale=0.05, size=(m.n, 3)).astype(np.float32)).cuda())
+        torch.cuda.synchronize()
+        want = sd.debye_profile(c, t, tab, m.q, ctx=sd.Context(0)).clone()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), f"replay {rep}"
+    host = c.cpu().numpy()
+    ref = oracle.profile(host, m.types, m.table, m.q)
+    assert np.max(np.abs(out.cpu().numpy() - ref) / ref) <= 1e-6
+    assert not torch.equal(out, eager)
