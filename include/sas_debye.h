@@ -195,6 +195,39 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
                                 void* stream);
 
 /*
+ * Orientation-averaged and hybrid profiles (approximate at a stated
+ * tolerance).  Eq. 1 averages |A(q,u)|^2, A = sum_j f_j exp(i q u.r_j), over
+ * directions u; a product rule with L+1 Gauss-Legendre nodes in cos(theta)
+ * and 2L+1 uniform nodes in phi averages it to relative accuracy about tol
+ * when L >= q R + O((q R)^(1/3)) (R: largest distance from the centre), at
+ * a cost of (L+1)(2L+1) N per q against N^2/2 for the direct sum: cheaper
+ * at low q, as the Background section argues (O(q^2 D^2) directions).
+ *
+ * sas_orient_degree: the L used for q, R and tol (host only; -1 for invalid
+ * arguments).
+ *
+ * sas_debye_profile_hybrid: mode SAS_HYBRID_AUTO averages the leading q values
+ * for which (L+1)(2L+1) N costs less than the direct sum and sums the rest
+ * directly (uniform rest: recurrence; otherwise direct form);
+ * SAS_HYBRID_ORIENT_ALL averages every q (at most 2^17 directions per chunk
+ * of 16 q, SAS_ERR_UNSUPPORTED beyond); SAS_HYBRID_DIRECT_ALL is the direct
+ * sum.  tol in [1e-15, 1e-2].  *n_orient (host, may be NULL) receives the
+ * number of leading q values that were averaged.  t <= SAS_MAX_TYPES.  This
+ * call synchronises `stream` once (it reads the molecule's radius back to
+ * choose L).  If the workspace is smaller than the query returns, fewer q
+ * values are averaged (AUTO) or the call fails (ORIENT_ALL).
+ */
+#define SAS_HYBRID_AUTO 0
+#define SAS_HYBRID_ORIENT_ALL 1
+#define SAS_HYBRID_DIRECT_ALL 2
+int32_t sas_orient_degree(double q, double r_max, double tol);
+size_t sas_debye_workspace_size_hybrid(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int32_t mode);
+sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                    const float* table, int32_t t, const double* q, int32_t nq, double tol,
+                                    int32_t mode, double* I_out, void* workspace, size_t ws_bytes, void* stream,
+                                    int32_t* n_orient);
+
+/*
  * Tuning controls (optional).  sas_set_variant forces the forward tile shape
  * for subsequent calls on ctx: bj = atoms per J block (64, 128, 256 or 512;
  * 0 = automatic) and qc = q values per chunk (one of 16, 32, 64, 100, 128,

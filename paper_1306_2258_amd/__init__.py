@@ -33,6 +33,7 @@ from ._lib import SasError, check, load
 
 __all__ = [
     "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched", "debye_grad", "debye_grad_table",
+    "debye_profile_hybrid", "orient_degree",
     "BatchedPlan", "DebyeProfile", "debye_profile_autograd", "default_context",
 ]
 
@@ -280,6 +281,38 @@ def debye_grad(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q
                                 qh.ctypes.data_as(ctypes.c_void_p), nq, _ptr(w), _ptr(grad), _ptr(prof), _ptr(ws),
                                 ws.numel(), _stream(coords.device)), "sas_debye_grad")
     return (grad, prof) if with_profile else grad
+
+
+HYBRID_MODES = {"auto": 0, "orient": 1, "direct": 2}
+
+
+def orient_degree(q: float, r_max: float, tol: float) -> int:
+    """Quadrature degree L the orientation average uses for q, radius and tol."""
+    return int(load().sas_orient_degree(float(q), float(r_max), float(tol)))
+
+
+def debye_profile_hybrid(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, *, tol: float = 1e-9,
+                         mode: str = "auto", ctx: Optional[Context] = None):
+    """Profile with the leading q values averaged over orientations where that
+    is cheaper than the direct sum (approximate to about ``tol``); returns
+    (I float64 [Nq] on the GPU, number of averaged q values).  ``mode``
+    "orient" averages every q, "direct" none.  Synchronises the stream once."""
+    _check_inputs(coords, types, table)
+    ctx = ctx or default_context(coords.device)
+    qh = _q_host(q)
+    n, t, nq = coords.shape[0], table.shape[0], len(qh)
+    md = HYBRID_MODES[mode]
+    out = torch.empty(nq, dtype=torch.float64, device=coords.device)
+    nbytes = int(load().sas_debye_workspace_size_hybrid(ctx.handle, n, t, nq, md))
+    if nbytes == 0:
+        check(1, "sas_debye_workspace_size_hybrid")
+    ws = ctx.workspace(nbytes)
+    n_orient = ctypes.c_int32(0)
+    check(load().sas_debye_profile_hybrid(ctx.handle, _ptr(coords), _ptr(types), n, _ptr(table), t,
+                                          qh.ctypes.data_as(ctypes.c_void_p), nq, float(tol), md, _ptr(out),
+                                          _ptr(ws), ws.numel(), _stream(coords.device), ctypes.byref(n_orient)),
+          "sas_debye_profile_hybrid")
+    return out, int(n_orient.value)
 
 
 def debye_grad_table(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, dL_dI: torch.Tensor, *,

@@ -48,6 +48,10 @@ SIGNATURES = {
     "sas_get_variant": (ctypes.c_int, [P, P, P]),
     "sas_set_form": (ctypes.c_int, [P, ctypes.c_int]),
     "sas_get_form": (ctypes.c_int, [P, P]),
+    "sas_orient_degree": (I32, [ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "sas_debye_workspace_size_hybrid": (SZ, [P, I64, I32, I32, I32]),
+    "sas_debye_profile_hybrid": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, ctypes.c_double, I32, P, P, SZ, P,
+                                                P]),
     "sas_enable_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "sas_read_timing": (ctypes.c_int, [P, P, P, P, P]),
 }

@@ -17,7 +17,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsas_debye.so")
-SOURCES = ["sas_kernels.hip", "sas_tablegrad.hip", "sas_peratom.hip", "sas_adjoint.hip", "sas_api.hip"]
+SOURCES = ["sas_kernels.hip", "sas_tablegrad.hip", "sas_peratom.hip", "sas_adjoint.hip", "sas_orient.hip",
+           "sas_api.hip"]
 ARCH = "gfx950"
 
 

@@ -422,7 +422,7 @@ std::vector<char> upload_image(const Schedule& sc, const Layout& L, const QGrid&
 
 // Asynchronous upload through the context's pinned staging buffer.  The
 // buffer is reused once the previous upload from it has completed.
-sas_status stage_upload(sas_ctx* ctx, void* ws, const Layout& L, const std::vector<char>& img, hipStream_t hs) {
+sas_status stage_upload_to(sas_ctx* ctx, void* dst, const std::vector<char>& img, hipStream_t hs) {
   if (img.empty()) return SAS_OK;
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (ctx->pinned_used) SAS_HIP(hipEventSynchronize(ctx->pinned_ev));
@@ -436,10 +436,14 @@ sas_status stage_upload(sas_ctx* ctx, void* ws, const Layout& L, const std::vect
   }
   if (!ctx->pinned_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
   std::memcpy(ctx->pinned, img.data(), img.size());
-  SAS_HIP(hipMemcpyAsync(static_cast<char*>(ws) + L.upload, ctx->pinned, img.size(), hipMemcpyHostToDevice, hs));
+  SAS_HIP(hipMemcpyAsync(dst, ctx->pinned, img.size(), hipMemcpyHostToDevice, hs));
   SAS_HIP(hipEventRecord(ctx->pinned_ev, hs));
   ctx->pinned_used = true;
   return SAS_OK;
+}
+
+sas_status stage_upload(sas_ctx* ctx, void* ws, const Layout& L, const std::vector<char>& img, hipStream_t hs) {
+  return stage_upload_to(ctx, static_cast<char*>(ws) + L.upload, img, hs);
 }
 
 // Enqueue pack -> forward -> reduce for a prepared schedule.  The upload
@@ -1032,6 +1036,330 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
     SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));
   }
   SAS_HIP(sas::launch_grad_reduce(a, n, sc.nchunks_adj, reinterpret_cast<const int32_t*>(w + L.perm), grad_out, hs));
+  return SAS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Orientation-averaged and hybrid profiles
+// ---------------------------------------------------------------------------
+namespace {
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+constexpr int64_t kOrientCapAll = int64_t(1) << 17;  // directions per chunk when every q is averaged
+constexpr int64_t kOrientBlocksTarget = 4096;          // work-groups the amplitude kernel aims for
+// Issue cost per unit, in VALU instructions (measured mixes): a pair*q of the
+// type-form recurrence, of the direct form, and an atom*direction*q of the
+// orientation kernel.
+constexpr double kCostRecurrence = 3.3, kCostDirect = 14.4, kCostOrient = 21.0;
+
+// Gauss-Legendre rule of n points on [-1, 1]: roots of P_n by Newton's method
+// from cos(pi (i + 3/4) / (n + 1/2)), P_n and P_n' from the three-term
+// recurrence, weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) p0 = 1.0;
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-15 * std::fmax(1.0, std::fabs(z))) {
+        // derivative at the converged root for the weight
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        if (n == 1) p0 = 1.0;
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        break;
+      }
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+int32_t orient_degree(double q, double r_max, double tol) {
+  const double qr = q * r_max;
+  const double d = std::min(15.0, std::max(4.0, -std::log10(tol)));
+  return static_cast<int32_t>(std::ceil(qr + 0.25 * d * std::cbrt(qr) + 0.6 * d));
+}
+
+struct OrientPlan {
+  int32_t nq_o = 0;  // leading q values averaged over orientations
+  std::vector<sas::OrientChunk> chunks;
+  std::vector<double> gl;  // node, weight pairs
+  int64_t total_blocks = 0;
+  int32_t parts = 1, atoms_per_part = 0;
+  int64_t apart_elems = 0;  // double2 values
+  int32_t ldo = 0;          // row stride of the orientation table
+};
+
+OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, double tol) {
+  OrientPlan p;
+  p.nq_o = nq_o;
+  if (nq_o <= 0) return p;
+  const int32_t nch = (nq_o + sas::kOrientQ - 1) / sas::kOrientQ;
+  p.ldo = nch * sas::kOrientQ;
+  int64_t blk = 0;
+  for (int32_t c = 0; c < nch; ++c) {
+    sas::OrientChunk ch{};
+    ch.m0 = c * sas::kOrientQ;
+    ch.nq = std::min(sas::kOrientQ, nq_o - ch.m0);
+    const int32_t L = orient_degree(q[ch.m0 + ch.nq - 1], r_max, tol);
+    ch.nth = L + 1;
+    ch.nph = 2 * L + 1;
+    ch.gl_off = static_cast<int32_t>(p.gl.size() / 2);
+    std::vector<double> x(ch.nth), w(ch.nth);
+    gauss_legendre(ch.nth, x.data(), w.data());
+    for (int32_t i = 0; i < ch.nth; ++i) {
+      p.gl.push_back(x[i]);
+      p.gl.push_back(w[i]);
+    }
+    ch.blk_off = blk;
+    blk += cdiv(static_cast<int64_t>(ch.nth) * ch.nph, int64_t(sas::kWave));
+    p.chunks.push_back(ch);
+  }
+  p.total_blocks = blk;
+  const int64_t max_parts = std::max<int64_t>(1, cdiv(n, int64_t(256)));
+  p.parts = static_cast<int32_t>(std::min(max_parts, std::max<int64_t>(1, cdiv(kOrientBlocksTarget, blk))));
+  p.atoms_per_part = static_cast<int32_t>(cdiv(cdiv(std::max<int64_t>(n, 1), int64_t(p.parts)),
+                                                        int64_t(sas::kPaSub)) * sas::kPaSub);
+  int64_t off = 0;
+  for (auto& ch : p.chunks) {
+    ch.a_off = off;
+    off += static_cast<int64_t>(p.parts) * ch.nth * ch.nph * sas::kOrientQ;
+  }
+  p.apart_elems = off;
+  return p;
+}
+
+// Workspace of the orientation part: upload block (chunks, rule, q values),
+// geometry, padded table and partial amplitudes.
+struct OrientLayout {
+  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, geom = 0;
+  size_t upload = 0, upload_bytes = 0, chunks = 0, gl = 0, qv = 0;
+  size_t tabo = 0, apart = 0, tabd = 0, direct = 0, total = 0;
+};
+
+OrientLayout orient_layout(int64_t n, int32_t T, int64_t n_pack, const OrientPlan& p, int32_t nq_d,
+                           size_t direct_bytes) {
+  OrientLayout L;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at = align_up(at + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  L.xyz = take(sizeof(double4) * n);
+  L.tsort = take(sizeof(int32_t) * n);
+  L.perm = take(sizeof(int32_t) * n);
+  L.bcount = take(sizeof(int32_t) * n_pack * T);
+  L.toff = take(sizeof(int32_t) * (T + 1));
+  L.geom = take(sizeof(double) * 4);
+  const size_t cb = align_up(sizeof(sas::OrientChunk) * p.chunks.size());
+  const size_t gb = align_up(sizeof(double) * p.gl.size());
+  const size_t qb = sizeof(double) * p.nq_o;
+  L.upload_bytes = cb + gb + qb;
+  L.upload = take(L.upload_bytes);
+  L.chunks = L.upload;
+  L.gl = L.upload + cb;
+  L.qv = L.upload + cb + gb;
+  L.tabo = take(sizeof(float) * static_cast<size_t>(T) * p.ldo);
+  L.apart = take(sizeof(double) * 2 * p.apart_elems);
+  L.tabd = take(sizeof(float) * static_cast<size_t>(T) * nq_d);
+  L.direct = take(direct_bytes);
+  L.total = at;
+  return L;
+}
+
+size_t direct_part_bytes(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq_d) {
+  if (nq_d <= 0) return 0;
+  const std::vector<int64_t> sizes{n};
+  const bool pa = use_per_atom(ctx, t, n);
+  size_t need = 0;
+  for (bool direct : {false, true})
+    need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq_d, 0, 0, direct, pa), t, nq_d).total);
+  return need;
+}
+
+// Bound on the orientation part's size: K directions per chunk at most cap.
+size_t orient_bound_bytes(int64_t n, int32_t t, int32_t nq, int64_t cap) {
+  const int64_t nch = cdiv(int64_t(nq), int64_t(sas::kOrientQ));
+  const int64_t blocks = nch * cdiv(cap, int64_t(sas::kWave));
+  const int64_t L = static_cast<int64_t>(std::sqrt(static_cast<double>(cap) / 2.0)) + 2;
+  size_t b = 0;
+  b += align_up(sizeof(double4) * n) + 2 * align_up(sizeof(int32_t) * n);
+  b += align_up(sizeof(int32_t) * cdiv(n, int64_t(sas::kPackBlock)) * t) + align_up(sizeof(int32_t) * (t + 1));
+  b += 256 + align_up(sizeof(sas::OrientChunk) * nch) + align_up(sizeof(double) * 2 * nch * (L + 1)) +
+       align_up(sizeof(double) * nq) + 256;
+  b += align_up(sizeof(float) * t * nch * sas::kOrientQ);
+  if (cap > 0) b += align_up(sizeof(double) * 2 * (kOrientBlocksTarget + blocks) * sas::kWave * sas::kOrientQ);
+  b += align_up(sizeof(float) * t * static_cast<size_t>(nq));
+  return b;
+}
+
+int64_t orient_cap(int64_t n, int32_t mode, bool uniform) {
+  if (mode == SAS_HYBRID_ORIENT_ALL) return kOrientCapAll;
+  const double cd = uniform ? kCostRecurrence : kCostDirect;
+  return std::max<int64_t>(1, static_cast<int64_t>(0.5 * static_cast<double>(std::max<int64_t>(n - 1, 0)) * cd /
+                                                   kCostOrient));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sas_orient_degree(double q, double r_max, double tol) {
+  if (!(q >= 0.0) || !(r_max >= 0.0) || !(tol > 0.0) || !std::isfinite(q) || !std::isfinite(r_max)) return -1;
+  return orient_degree(q, r_max, tol);
+}
+
+size_t sas_debye_workspace_size_hybrid(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int32_t mode) {
+  if (check_sizes(n, t, nq, SAS_MAX_TYPES) != SAS_OK) return 0;
+  if (mode < SAS_HYBRID_AUTO || mode > SAS_HYBRID_DIRECT_ALL) return 0;
+  const int64_t cap = std::max(orient_cap(n, mode, true), orient_cap(n, mode, false));
+  // (the pack, geometry and table-copy regions precede the direct part in every mode)
+  const size_t orient = orient_bound_bytes(n, t, nq, mode == SAS_HYBRID_DIRECT_ALL ? 0 : cap);
+  size_t direct = 0;  // whichever number of q values is left to the direct sum
+  for (int32_t nq_d = 1; nq_d <= nq; ++nq_d) direct = std::max(direct, direct_part_bytes(ctx, n, t, nq_d));
+  return orient + direct + 4096;
+}
+
+sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                    const float* table, int32_t t, const double* q, int32_t nq, double tol,
+                                    int32_t mode, double* I_out, void* workspace, size_t ws_bytes, void* stream,
+                                    int32_t* n_orient) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TYPES);
+  if (st != SAS_OK) return st;
+  if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
+  if (!(tol >= 1e-15 && tol <= 1e-2)) return fail(SAS_ERR_INVALID_ARG, "tol %g outside [1e-15, 1e-2]", tol);
+  if (mode < SAS_HYBRID_AUTO || mode > SAS_HYBRID_DIRECT_ALL) return fail(SAS_ERR_INVALID_ARG, "unknown mode %d", mode);
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
+  if (st != SAS_OK) return st;
+  if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+
+  // 1. pack (type sort) and geometry; the radius decides the quadrature, so
+  //    it is read back here (the one synchronisation of this call)
+  const Schedule sp = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  OrientPlan none;
+  OrientLayout L0 = orient_layout(n, t, sp.n_pack, none, 0, 0);
+  if (ws_bytes < L0.total) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L0.total);
+  double geom[4] = {0.0, 0.0, 0.0, 0.0};
+  if (mode != SAS_HYBRID_DIRECT_ALL && n > 0) {
+    Layout Lp;
+    Lp.desc = 0;
+    SAS_HIP(sas::launch_pack(coords, types, view_of(sp, workspace, Lp), 1, sp.n_pack, t,
+                             reinterpret_cast<int32_t*>(w + L0.bcount), reinterpret_cast<int32_t*>(w + L0.toff),
+                             reinterpret_cast<double4*>(w + L0.xyz), reinterpret_cast<int32_t*>(w + L0.tsort),
+                             reinterpret_cast<int32_t*>(w + L0.perm), hs));
+    SAS_HIP(sas::launch_geometry(reinterpret_cast<const double4*>(w + L0.xyz), n, reinterpret_cast<double*>(w + L0.geom),
+                                 hs));
+    SAS_HIP(hipMemcpyAsync(geom, w + L0.geom, sizeof(geom), hipMemcpyDeviceToHost, hs));
+    SAS_HIP(hipStreamSynchronize(hs));
+  }
+  const double r_max = geom[3];
+
+  // 2. the split: the leading q values whose orientation average costs less
+  //    than the direct sum (directions grow with q, so it is a prefix)
+  int32_t nq_o = 0;
+  if (mode == SAS_HYBRID_ORIENT_ALL) {
+    nq_o = nq;
+  } else if (mode == SAS_HYBRID_AUTO && n > 1) {
+    const double cd = grid.uniform ? kCostRecurrence : kCostDirect;
+    const double direct_cost = 0.5 * static_cast<double>(n) * static_cast<double>(n - 1) * cd;
+    while (nq_o < nq) {
+      const int64_t L = orient_degree(q[nq_o], r_max, tol);
+      const double k = static_cast<double>(L + 1) * (2 * L + 1);
+      if (k * static_cast<double>(n) * kCostOrient >= direct_cost) break;
+      ++nq_o;
+    }
+  }
+  const int64_t cap = orient_cap(n, mode, grid.uniform);
+  OrientPlan plan;
+  OrientLayout L;
+  for (;;) {
+    plan = plan_orient(n, q, nq_o, r_max, tol);
+    bool over = false;
+    for (const auto& ch : plan.chunks) over = over || static_cast<int64_t>(ch.nth) * ch.nph > cap;
+    const int32_t nq_d = nq - nq_o;
+    L = orient_layout(n, t, sp.n_pack, plan, nq_d, direct_part_bytes(ctx, n, t, nq_d));
+    if (!over && L.total <= ws_bytes) break;
+    if (mode == SAS_HYBRID_ORIENT_ALL) {
+      if (over) return fail(SAS_ERR_UNSUPPORTED, "orientation average needs more than %lld directions", (long long)cap);
+      return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+    }
+    if (nq_o == 0) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+    nq_o = std::max(0, ((nq_o - 1) / sas::kOrientQ) * sas::kOrientQ);  // drop the last chunk
+  }
+
+  // 3. orientation average of the leading q values
+  if (nq_o > 0) {
+    std::vector<char> img(L.upload_bytes, 0);
+    std::memcpy(img.data() + (L.chunks - L.upload), plan.chunks.data(), sizeof(sas::OrientChunk) * plan.chunks.size());
+    std::memcpy(img.data() + (L.gl - L.upload), plan.gl.data(), sizeof(double) * plan.gl.size());
+    std::memcpy(img.data() + (L.qv - L.upload), q, sizeof(double) * nq_o);
+    st = stage_upload_to(ctx, w + L.upload, img, hs);
+    if (st != SAS_OK) return st;
+    SAS_HIP(sas::launch_copy_cols(table, t, nq, 0, nq_o, plan.ldo, reinterpret_cast<float*>(w + L.tabo), hs));
+    sas::OrientArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.chunks = reinterpret_cast<const sas::OrientChunk*>(w + L.chunks);
+    a.nchunks = static_cast<int32_t>(plan.chunks.size());
+    a.T = t;
+    a.gl = reinterpret_cast<const double*>(w + L.gl);
+    a.xyz = reinterpret_cast<const double4*>(w + L0.xyz);
+    a.tsort = reinterpret_cast<const int32_t*>(w + L0.tsort);
+    a.tabp = reinterpret_cast<const float*>(w + L.tabo);
+    a.ldt = plan.ldo;
+    a.n = static_cast<int32_t>(n);
+    a.qv = reinterpret_cast<const double*>(w + L.qv);
+    a.center = reinterpret_cast<const double*>(w + L0.geom);
+    a.parts = plan.parts;
+    a.atoms_per_part = plan.atoms_per_part;
+    a.apart = reinterpret_cast<double2*>(w + L.apart);
+    SAS_HIP(sas::launch_orient(a, plan.total_blocks, nq_o, I_out, hs));
+  }
+
+  // 4. direct sum for the rest, on a compact copy of their table columns
+  const int32_t nq_d = nq - nq_o;
+  if (nq_d > 0) {
+    QGrid gd;
+    st = classify_q(q + nq_o, nq_d, &gd);
+    if (st != SAS_OK) return st;
+    float* tabd = reinterpret_cast<float*>(w + L.tabd);
+    SAS_HIP(sas::launch_copy_cols(table, t, nq, nq_o, nq_d, nq_d, tabd, hs));
+    const Schedule sd = make_schedule(ctx, std::vector<int64_t>{n}, t, nq_d, 0, 0, !gd.uniform || ctx->force_direct,
+                                      use_per_atom(ctx, t, n));
+    const Layout Ld = make_layout(sd, t, nq_d);
+    void* wd = w + L.direct;
+    st = stage_upload(ctx, wd, Ld, upload_image(sd, Ld, gd), hs);
+    if (st != SAS_OK) return st;
+    st = enqueue_forward(ctx, sd, Ld, coords, types, tabd, t, nq_d, gd.q0, gd.dq, I_out + nq_o, wd, hs);
+    if (st != SAS_OK) return st;
+  }
+  if (n_orient) *n_orient = nq_o;
   return SAS_OK;
 }
 

@@ -22,6 +22,7 @@ constexpr double kPiB = 0x1.0b4611a600000p-33;
 constexpr double kPiC = 0x1.3198a2e037073p-68;
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
+constexpr double kTwoPi = 0x1.921fb54442d18p+2;
 
 // 1/n! for the Taylor coefficients (n! is exact in FP64 up to 22!).
 constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }

@@ -105,6 +105,40 @@ hipError_t launch_table_grad_final(int64_t n_slices, const double* gslices, cons
                                    const float* table, int32_t T, int32_t Nq, double q0, double dq, const double* qdev,
                                    const double* w, double* grad_table, hipStream_t st);
 
+// Orientation-averaged profile (sas_orient.hip).
+constexpr int kOrientQ = 16;  // q values per orientation chunk (one quadrature per chunk)
+
+struct OrientChunk {
+  int32_t m0, nq;    // first q (into the orientation q list) and count, m0 = chunk * kOrientQ
+  int32_t nth, nph;  // Gauss-Legendre nodes in cos(theta), uniform nodes in phi
+  int32_t gl_off;    // first node of this chunk in the node table
+  int32_t pad;
+  int64_t blk_off;   // first direction block (of 64) of this chunk
+  int64_t a_off;     // first partial amplitude of this chunk: [parts][nth * nph][kOrientQ]
+};
+
+struct OrientArgs {
+  const OrientChunk* chunks;
+  int32_t nchunks;
+  int32_t T;
+  const double* gl;      // [nodes][2]: x, weight (weights of one rule sum to 2)
+  const double4* xyz;    // FP64 coordinates of the structure
+  const int32_t* tsort;  // their type ids
+  const float* tabp;     // [T][ldt]: f_t at the orientation q values, zero beyond
+  int32_t ldt;
+  int32_t n;
+  const double* qv;      // orientation q values
+  const double* center;  // [3] (k_geometry output)
+  int32_t parts;         // the atoms are split into parts (grid.y)
+  int32_t atoms_per_part;
+  double2* apart;        // partial amplitudes
+};
+
+hipError_t launch_geometry(const double4* xyz, int64_t n, double* out, hipStream_t st);
+hipError_t launch_orient(const OrientArgs& a, int64_t total_blocks, int32_t nq_o, double* I_out, hipStream_t st);
+hipError_t launch_copy_cols(const float* src, int32_t T, int32_t ld_src, int32_t col0, int32_t ncols, int32_t ldt,
+                            float* dst, hipStream_t st);
+
 // Per-atom form (sas_peratom.hip).
 hipError_t launch_pack_plain(const float* coords, const int32_t* types, int64_t n_total, int32_t T, double4* xyz,
                              int32_t* tsort, int32_t* perm, hipStream_t st);

@@ -169,3 +169,47 @@ def test_sine_polynomial_constants_match_their_fit():
     exact = np.sin(np.pi * x)
     nz = exact != 0
     assert np.max(np.abs(approx[nz] - exact[nz]) / np.abs(exact[nz])) < 5e-8
+
+
+def test_orient_degree_rule(lib):
+    """The quadrature degree grows with q R, is at least 0.6 digits + q R,
+    and rejects invalid arguments."""
+    import math
+
+    d = [lib.sas_orient_degree(q, 30.0, 1e-10) for q in np.linspace(0.0, 1.0, 21)]
+    assert all(b >= a for a, b in zip(d, d[1:]))
+    for q in (0.0, 0.1, 0.5, 1.0):
+        qr = q * 30.0
+        assert lib.sas_orient_degree(q, 30.0, 1e-10) == math.ceil(qr + 2.5 * qr ** (1 / 3) + 6.0)
+    assert lib.sas_orient_degree(0.5, 30.0, 1e-4) < lib.sas_orient_degree(0.5, 30.0, 1e-12)
+    assert lib.sas_orient_degree(-1.0, 30.0, 1e-8) == -1
+    assert lib.sas_orient_degree(0.1, 30.0, 0.0) == -1
+
+
+def test_orient_degree_reaches_its_tolerance():
+    """With the library's degree, a product Gauss-Legendre x uniform rule
+    (written here in numpy) averages Eq. 1 to within 1e-8 of the FP64 Debye
+    sum for a small molecule over 0 < q R <= 25."""
+    import oracle
+    import workloads as W
+    from paper_1306_2258_amd import _lib
+
+    lib = _lib.load()
+    m = W.random_molecule(1700, 120, 1, extent=30.0)
+    c = m.coords.astype(np.float64)
+    c = c - c.mean(axis=0)
+    R = float(np.max(np.linalg.norm(c, axis=1)))
+    for qr in (0.5, 3.0, 10.0, 25.0):
+        q = np.array([qr / R])
+        tab = W.gaussian_table((1.0, 2.0, 3.0, 4.0, 5.0), 1.0, q)
+        L = lib.sas_orient_degree(float(q[0]), R, 1e-10)
+        x, wx = np.polynomial.legendre.leggauss(L + 1)
+        phi = 2 * np.pi * np.arange(2 * L + 1) / (2 * L + 1)
+        st = np.sqrt(1 - x * x)
+        U = np.stack([np.outer(st, np.cos(phi)).ravel(), np.outer(st, np.sin(phi)).ravel(),
+                      np.repeat(x, len(phi))], 1)
+        wk = np.repeat(wx, len(phi)) / (2 * len(phi))
+        A = np.exp(1j * q[0] * (U @ c.T)) @ tab[m.types, 0].astype(np.float64)
+        I = float(np.sum(wk * np.abs(A) ** 2))
+        ref = float(oracle.profile(m.coords, m.types, tab, q)[0])
+        assert abs(I - ref) / ref < 1e-8, (qr, L, I, ref)

@@ -1,0 +1,146 @@
+"""GPU checks of the orientation-averaged and hybrid profiles against the FP64
+Debye oracle (Eq. 1 averaged over directions equals Eq. 2).
+
+The orientation average is approximate by construction; with tol = 1e-10 the
+quadrature degree leaves its error far below the 1e-6 per-q bar, which the
+tests apply unchanged.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_2258_amd as mod
+
+    return mod
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(m):
+    import torch
+
+    return (torch.from_numpy(m.coords).cuda(), torch.from_numpy(m.types).cuda(), torch.from_numpy(m.table).cuda())
+
+
+def rel_err(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 400])
+def test_orientation_average_all_q(sd, n):
+    say(f"orientation average of every q, N={n}")
+    m = W.random_molecule(1800 + n, n, 40, t=3, q0=0.0, q1=0.8, extent=3.0 * n ** (1 / 3) + 8.0)
+    c, t, tab = to_dev(m)
+    I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10, mode="orient")
+    assert n_o == len(m.q)
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    err = rel_err(I.cpu().numpy(), ref)
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() <= TOL
+
+
+def test_orientation_average_types_and_log_grid(sd):
+    say("orientation average, T=17 non-separable, log-spaced q")
+    m = W.random_molecule(1820, 900, 0, t=17, q=W.log_grid(1e-3, 0.6, 50), extent=26.0,
+                          widths=np.linspace(0.2, 1.5, 17))
+    c, t, tab = to_dev(m)
+    I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10, mode="orient")
+    assert n_o == len(m.q)
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    assert rel_err(I.cpu().numpy(), ref).max() <= TOL
+
+
+def test_direct_mode_equals_plain_profile(sd):
+    say("hybrid in direct mode is the plain profile, bitwise")
+    m = W.random_molecule(1830, 1200, 77, q0=0.0, q1=1.0, extent=30.0)
+    c, t, tab = to_dev(m)
+    I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, mode="direct")
+    assert n_o == 0
+    assert np.array_equal(I.cpu().numpy(), sd.debye_profile(c, t, tab, m.q).cpu().numpy())
+
+
+def test_hybrid_auto_globular(sd):
+    """A 20,000-atom globule (R about 38 A) on 100 q in [0, 1]: the low q
+    values are averaged, the rest summed directly; sampled q of both parts
+    against the oracle."""
+    say("hybrid auto, globular N=20000, Nq=100")
+    rng_seed = 13062258 + 60
+    n = 20000
+    rng = W.rng_for(rng_seed)
+    pts = W.uniform_ball_min_sep(rng, n, W.globular_radius(n), 1.0)
+    types = W.draw_types(rng, n)
+    q = W.q_grid(0.0, 1.0, 100)
+    m = W.Molecule("globular_20k", np.ascontiguousarray(pts, dtype=np.float32), types,
+                   W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
+    c, t, tab = to_dev(m)
+    I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
+    print(f"averaged q values: {n_o}")
+    assert 0 < n_o < len(q)
+    pick = np.array(sorted({0, 1, n_o // 2, n_o - 1, n_o, min(n_o + 7, 99), 99}))
+    ref = oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
+    err = rel_err(I.cpu().numpy()[pick], ref)
+    print("sampled errors", " ".join(f"{e:.2e}" for e in err))
+    assert err.max() <= TOL
+
+
+def test_hybrid_small_workspace(sd):
+    """With a workspace too small for the averaged part the automatic mode
+    averages fewer q values (still exact where it sums directly); the
+    all-orientation mode refuses."""
+    import ctypes
+
+    import torch
+
+    from paper_1306_2258_amd import _lib
+
+    say("hybrid with a reduced workspace")
+    lib = _lib.load()
+    n = 6000
+    rng = W.rng_for(13062258 + 61)
+    pts = W.uniform_ball_min_sep(rng, n, W.globular_radius(n), 1.0)
+    types = W.draw_types(rng, n)
+    q = W.q_grid(0.0, 0.6, 40)
+    m = W.Molecule("globular_6k", np.ascontiguousarray(pts, dtype=np.float32), types,
+                   W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
+    c, t, tab = to_dev(m)
+    ctx = sd.Context(0)
+    full, n_full = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10, ctx=ctx)
+    assert n_full > 0
+    need_direct = lib.sas_debye_workspace_size_hybrid(ctx.handle, n, 5, len(q), 2)
+    ws = torch.empty(need_direct, dtype=torch.uint8, device="cuda")
+    out = torch.empty(len(q), dtype=torch.float64, device="cuda")
+    n_o = ctypes.c_int32(-1)
+    qh = np.ascontiguousarray(q)
+    st = lib.sas_debye_profile_hybrid(ctx.handle, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(t.data_ptr()), n,
+                                      ctypes.c_void_p(tab.data_ptr()), 5, qh.ctypes.data_as(ctypes.c_void_p),
+                                      len(q), 1e-10, 0, ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(ws.data_ptr()), ws.numel(), None, ctypes.byref(n_o))
+    assert st == 0 and 0 <= n_o.value < n_full
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    assert rel_err(out.cpu().numpy(), ref).max() <= TOL
+    assert rel_err(full.cpu().numpy(), ref).max() <= TOL
+    st = lib.sas_debye_profile_hybrid(ctx.handle, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(t.data_ptr()), n,
+                                      ctypes.c_void_p(tab.data_ptr()), 5, qh.ctypes.data_as(ctypes.c_void_p),
+                                      len(q), 1e-10, 1, ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(ws.data_ptr()), 4096, None, ctypes.byref(n_o))
+    assert st == 4
