@@ -1049,10 +1049,20 @@ namespace {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int64_t kOrientCapAll = int64_t(1) << 17;  // directions per chunk when every q is averaged
 constexpr int64_t kOrientBlocksTarget = 4096;          // work-groups the amplitude kernel aims for
-// Issue cost per unit, in VALU instructions (measured mixes): a pair*q of the
-// type-form recurrence, of the direct form, and an atom*direction*q of the
-// orientation kernel.
-constexpr double kCostRecurrence = 3.3, kCostDirect = 14.4, kCostOrient = 21.0;
+// Time per unit, in pair*q steps of the type-form recurrence (measured on
+// MI355X): the per-pair set-up of the recurrence (about 66 steps), a step of
+// the direct form (4.3) and its set-up (5), and an atom*direction*q of the
+// orientation kernel (9).
+constexpr double kSetupRecurrence = 66.0, kStepDirect = 4.3, kSetupDirect = 5.0, kCostOrient = 9.0;
+
+// Steps the forward kernel runs for nq q values (chunks padded to templates).
+double direct_steps(int32_t nq, bool uniform) {
+  if (nq <= 0) return 0.0;
+  if (!uniform) return kSetupDirect + kStepDirect * 32.0 * ((nq + 31) / 32);
+  const int32_t nch = (nq + 199) / 200;
+  const int32_t qc = (nq + nch - 1) / nch;
+  return kSetupRecurrence * nch + static_cast<double>(nch) * pick_qc_template(qc, false);
+}
 
 // Gauss-Legendre rule of n points on [-1, 1]: roots of P_n by Newton's method
 // from cos(pi (i + 3/4) / (n + 1/2)), P_n and P_n' from the three-term
@@ -1212,10 +1222,12 @@ size_t orient_bound_bytes(int64_t n, int32_t t, int32_t nq, int64_t cap) {
   return b;
 }
 
+// Directions per chunk the automatic split can choose: an averaged q must cost
+// less than the direct steps it saves (at most twice a step, with padding).
 int64_t orient_cap(int64_t n, int32_t mode, bool uniform) {
   if (mode == SAS_HYBRID_ORIENT_ALL) return kOrientCapAll;
-  const double cd = uniform ? kCostRecurrence : kCostDirect;
-  return std::max<int64_t>(1, static_cast<int64_t>(0.5 * static_cast<double>(std::max<int64_t>(n - 1, 0)) * cd /
+  const double step = uniform ? 1.0 : kStepDirect;
+  return std::max<int64_t>(1, static_cast<int64_t>(static_cast<double>(std::max<int64_t>(n - 1, 0)) * step /
                                                    kCostOrient));
 }
 
@@ -1287,13 +1299,23 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   if (mode == SAS_HYBRID_ORIENT_ALL) {
     nq_o = nq;
   } else if (mode == SAS_HYBRID_AUTO && n > 1) {
-    const double cd = grid.uniform ? kCostRecurrence : kCostDirect;
-    const double direct_cost = 0.5 * static_cast<double>(n) * static_cast<double>(n - 1) * cd;
-    while (nq_o < nq) {
-      const int64_t L = orient_degree(q[nq_o], r_max, tol);
-      const double k = static_cast<double>(L + 1) * (2 * L + 1);
-      if (k * static_cast<double>(n) * kCostOrient >= direct_cost) break;
-      ++nq_o;
+    // the chunk-aligned split with the least estimated time, in pair steps:
+    // averaged chunks cost K n kCostOrient per q against n(n-1)/2 pairs
+    // running the direct kernel's steps (set-up, padding) over the rest
+    const double pairs = 0.5 * static_cast<double>(n) * static_cast<double>(n - 1);
+    double best = pairs * direct_steps(nq, grid.uniform), orient = 0.0;
+    for (int32_t m0 = 0; m0 < nq; m0 += sas::kOrientQ) {
+      const int32_t m1 = std::min(nq, m0 + sas::kOrientQ);
+      const int64_t L = orient_degree(q[m1 - 1], r_max, tol);
+      orient += static_cast<double>(L + 1) * (2 * L + 1) * (m1 - m0) * static_cast<double>(n) * kCostOrient;
+      QGrid rest;
+      const bool uni = m1 < nq && classify_q(q + m1, nq - m1, &rest) == SAS_OK && rest.uniform;
+      const double total = orient + pairs * direct_steps(nq - m1, uni);
+      if (total < best) {
+        best = total;
+        nq_o = m1;
+      }
+      if (orient >= best) break;
     }
   }
   const int64_t cap = orient_cap(n, mode, grid.uniform);

@@ -79,24 +79,27 @@ def test_direct_mode_equals_plain_profile(sd):
     assert np.array_equal(I.cpu().numpy(), sd.debye_profile(c, t, tab, m.q).cpu().numpy())
 
 
-def test_hybrid_auto_globular(sd):
-    """A 20,000-atom globule (R about 38 A) on 100 q in [0, 1]: the low q
-    values are averaged, the rest summed directly; sampled q of both parts
-    against the oracle."""
-    say("hybrid auto, globular N=20000, Nq=100")
-    rng_seed = 13062258 + 60
-    n = 20000
-    rng = W.rng_for(rng_seed)
+def _globule(n, q, seed):
+    rng = W.rng_for(seed)
     pts = W.uniform_ball_min_sep(rng, n, W.globular_radius(n), 1.0)
     types = W.draw_types(rng, n)
-    q = W.q_grid(0.0, 1.0, 100)
-    m = W.Molecule("globular_20k", np.ascontiguousarray(pts, dtype=np.float32), types,
-                   W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
+    return W.Molecule(f"globular_{n}", np.ascontiguousarray(pts, dtype=np.float32), types,
+                      W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
+
+
+@pytest.mark.parametrize("q1", [0.15, 1.0])
+def test_hybrid_auto_globular(sd, q1):
+    """A 20,000-atom globule (R about 38 A) on 100 q in [0, q1]: the split the
+    cost model chooses (all averaged at low q; on [0, 1] whatever is cheaper),
+    sampled q of both parts against the oracle."""
+    say(f"hybrid auto, globular N=20000, Nq=100 on [0, {q1}]")
+    m = _globule(20000, W.q_grid(0.0, q1, 100), 13062258 + 60)
     c, t, tab = to_dev(m)
     I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
     print(f"averaged q values: {n_o}")
-    assert 0 < n_o < len(q)
-    pick = np.array(sorted({0, 1, n_o // 2, n_o - 1, n_o, min(n_o + 7, 99), 99}))
+    if q1 < 0.5:
+        assert n_o == len(m.q)
+    pick = np.array(sorted({0, 1, max(n_o // 2, 0), max(n_o - 1, 0), min(n_o, 99), min(n_o + 7, 99), 99}))
     ref = oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
     err = rel_err(I.cpu().numpy()[pick], ref)
     print("sampled errors", " ".join(f"{e:.2e}" for e in err))
@@ -119,7 +122,7 @@ def test_hybrid_small_workspace(sd):
     rng = W.rng_for(13062258 + 61)
     pts = W.uniform_ball_min_sep(rng, n, W.globular_radius(n), 1.0)
     types = W.draw_types(rng, n)
-    q = W.q_grid(0.0, 0.6, 40)
+    q = W.q_grid(0.0, 0.12, 40)
     m = W.Molecule("globular_6k", np.ascontiguousarray(pts, dtype=np.float32), types,
                    W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
     c, t, tab = to_dev(m)

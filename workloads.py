@@ -258,6 +258,17 @@ def dna_rod_50k(n: int = 50000, nq: int = 200, seed: int = BASE_SEED + 2, q=None
     return _finish("dna_rod_50k", pts.copy(), types.copy(), gaussian_table(TYPE_Z, TYPE_B, q), q)
 
 
+def globular(n: int, nq: int = 200, q1: float = 1.0, seed: int = BASE_SEED + 70) -> Molecule:
+    """n atoms in a sphere at the 10,000-atom workload's density (1 A minimum
+    separation), the 5-type mix, nq q on [0, q1]: a large compact molecule,
+    the case where orientation averaging pays at low q."""
+    rng = rng_for(seed)
+    pts = uniform_ball_min_sep(rng, n, globular_radius(n), 1.0)
+    types = draw_types(rng, n)
+    q = q_grid(0.0, q1, nq)
+    return _finish(f"globular_{n}", pts, types, gaussian_table(TYPE_Z, TYPE_B, q), q)
+
+
 def globular_radius(n: int) -> float:
     """Radius that keeps the 10,000-atom workload's density for n atoms."""
     return (3.0 * n / (4.0 * math.pi * GLOBULAR_DENSITY)) ** (1.0 / 3.0)
