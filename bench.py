@@ -44,8 +44,8 @@ BASE_SEED_PER_ATOM = 13062258 + 50
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_valu.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1306_2258_amd", "csrc", f)
-                  for f in ("sas_kernels.hip", "sas_forward.hpp", "sas_device.hpp", "sas_schedule.hpp",
-                            "sas_kernels.hpp")]
+                  for f in ("sas_kernels.hip", "sas_forward_kernel.hpp", "sas_forward.hpp", "sas_device.hpp",
+                            "sas_schedule.hpp", "sas_kernels.hpp")]
 
 
 def kernel_source_hash() -> str:
