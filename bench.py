@@ -118,7 +118,13 @@ def cpu_baseline(m, budget_q=(50, 100, 150, 199)):
     oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
     dt = time.perf_counter() - t0
     work = m.n * (m.n - 1) / 2.0 * len(pick)
-    return {"value": work / dt, "unit": "pair*q/s", "cores": threads, "kind": "oracle",
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": work / dt, "unit": "pair*q/s", "cores": threads, "kind": "oracle", "cpu": cpu,
             "sample": f"dna_rod_50k, all {m.n} atoms, {len(pick)} of the 200 q values "
                       f"(indices {list(budget_q)}), FP64, {dt:.1f} s"}
 
@@ -126,8 +132,8 @@ def cpu_baseline(m, budget_q=(50, 100, 150, 199)):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -159,15 +165,19 @@ def main(argv=None):
     ctx.enable_timing(True)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     e0.record()
     t0 = time.perf_counter()
+    marks[0].record()
     for k in range(args.steps):
         sd.debye_profile(coords, types, table, m.q, ctx=ctx, out=out)
+        marks[k + 1].record()
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_total = e0.elapsed_time(e1)
+    per_step = [marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps)]
     ctx.enable_timing(False)
     kt = ctx.read_timing()
     ms_step = ms_total / args.steps
@@ -203,6 +213,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": "dna_rod_50k", "atoms": m.n, "nq": len(m.q), "q_range": [0.0, 1.0], "types": 5,
                    "pair_q_per_step": work, "variant": {"bj": bj, "qc": qc}},
+        "ms_per_step_median": float(np.median(per_step)) if per_step else None,
+        "ms_per_step_min": float(np.min(per_step)) if per_step else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": stored_traffic(kname),
                      "kernel": kname, "kernel_ms": kern_ms, "flops_per_pair_q": FLOPS_PER_PAIR_Q,
@@ -221,6 +233,23 @@ def main(argv=None):
                               "median_rel_err": float(np.median(err)),
                               "kappa_at_max": float(ref[err.argmax(), 2] / ref[err.argmax(), 1])}
         log(f"max rel err vs oracle {err.max():.3e}")
+
+    # end to end from host arrays (the paper's GPU times include transfers):
+    # pageable host-to-device copies of coords, types and table, the profile,
+    # and I back on the host; median of 5
+    e2e = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c_h = torch.from_numpy(m.coords).to(dev)
+        t_h = torch.from_numpy(m.types).to(dev)
+        f_h = torch.from_numpy(m.table).to(dev)
+        sd.debye_profile(c_h, t_h, f_h, m.q, ctx=ctx).cpu()
+        e2e.append(time.perf_counter() - t1)
+    e2e_s = float(np.median(e2e))
+    result["end_to_end"] = {"ms": e2e_s * 1e3, "pair_q_per_s": work / e2e_s,
+                            "includes": "host-to-device copies of coords, types and table, the profile, "
+                                        "and the copy of I(q) back to the host"}
 
     if not args.no_extras:
         try:
@@ -297,6 +326,13 @@ def bench_batched(sd, W, torch, dev):
             sd.debye_profile(c, t, table, e.q, ctx=ctx2)
 
     res["ms_plain_launches"] = _time(plain, torch, reps=2)
+    # the batched result against the plain calls, structure by structure
+    batched = sd.debye_profile_batched(coords, types, e.offsets, table, e.q, ctx=ctx)
+    diff = 0.0
+    for s_idx, (c, t) in enumerate(views):
+        p = sd.debye_profile(c, t, table, e.q, ctx=ctx2)
+        diff = max(diff, float(((batched[s_idx] - p).abs() / p.abs()).max()))
+    res["max_rel_diff_vs_plain"] = diff
     best = min(res.get("ms_plan_replay", ms_batched), ms_batched)
     res["speedup_vs_plain"] = res["ms_plain_launches"] / best
     res["pair_q_per_s"] = work / (best / 1e3)
