@@ -132,7 +132,12 @@ struct OrientArgs {
   int32_t parts;         // the atoms are split into parts (grid.y)
   int32_t atoms_per_part;
   double2* apart;        // partial amplitudes
+  int32_t rot;           // 1: uniform q, walk exp(i q p) from the chunk's first q
+  double dq;             // the grid step (rot only)
 };
+// Largest phase step dq * r_max (radians) the rotation walk takes: its
+// increment exp(i dq p) - 1 then has modulus below 0.5.
+constexpr double kRotMaxStep = 0.5;
 
 hipError_t launch_geometry(const double4* xyz, int64_t n, double* out, hipStream_t st);
 hipError_t launch_orient(const OrientArgs& a, int64_t total_blocks, int32_t nq_o, double* I_out, hipStream_t st);

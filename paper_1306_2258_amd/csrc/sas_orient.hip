@@ -17,7 +17,17 @@
 //                   direction the projection p = u . (r - c) in FP64, per q the
 //                   sine and cosine of q p by the direct form's FP64 reduction
 //                   and FP32 polynomials; FP32 sums over each run, FP64 across
-//                   runs; one partial amplitude per (part, direction, q);
+//                   runs; one partial amplitude per (part, direction, q).
+//                   On a uniform grid whose step turns the phase of the
+//                   farthest atom by at most kRotMaxStep, the ROT variant
+//                   evaluates exp(i q p) only at the chunk's first q and
+//                   walks the rest by z <- z + z d, d = exp(i dq p) - 1:
+//                   four FP32 FMAs per q instead of a reduction and two
+//                   polynomials.  The start and d are FP64 (series
+//                   truncation below 1e-11) rounded once to FP32, so their
+//                   errors are plain roundings that differ from atom to
+//                   atom; an error common to all atoms would not average
+//                   out (see the kernel);
 //   k_orient_reduce one work-group per q: sum_k w_k |sum_parts A|^2 in a fixed
 //                   order.
 #include <hip/hip_runtime.h>
@@ -27,6 +37,26 @@
 #include "sas_schedule.hpp"
 
 namespace sas {
+
+// cos(x) - 1 and sin(x) for |x| <= kRotMaxStep by the Taylor series of
+// sincos_small, without forming cos(x) itself (1 + small would lose the small
+// part's low bits).
+struct StepInc {
+  double cm1, s;
+};
+__device__ __forceinline__ StepInc step_increment(double x) {
+  const double x2 = x * x;
+  double ps = add_vs(mul_vs(x2, kS11), kS9);
+  ps = fma_vvs(ps, x2, kS7);
+  ps = fma_vvs(ps, x2, kS5);
+  ps = fma_vvs(ps, x2, kS3);
+  double pc = add_vs(mul_vs(x2, kC12), kC10);
+  pc = fma_vvs(pc, x2, kC8);
+  pc = fma_vvs(pc, x2, kC6);
+  pc = fma_vvs(pc, x2, kC4);
+  pc = fma_vvs(pc, x2, kC2);
+  return StepInc{x2 * pc, fma(x * x2, ps, x)};
+}
 
 __global__ __launch_bounds__(1024) void k_geometry(const double4* __restrict__ xyz, int64_t n,
                                                    double* __restrict__ out) {
@@ -84,6 +114,7 @@ __device__ __forceinline__ int find_chunk(const OrientChunk* ch, int nchunks, in
   return lo;
 }
 
+template <bool ROT>
 __global__ __launch_bounds__(kWave, 3) void k_orient_amp(OrientArgs a) {
   constexpr int QO = kOrientQ;
   __shared__ double4 sj[kPaSub];
@@ -139,13 +170,35 @@ __global__ __launch_bounds__(kWave, 3) void k_orient_amp(OrientArgs a) {
     for (int jl = 0; jl < ns; ++jl) {
       asm volatile("" ::: "memory");
       const double4 p = sj[jl];
-      const double rp = fma(uz, p.z, fma(uy, p.y, ux * p.x)) * kOneOverPi;
+      const double pd = fma(uz, p.z, fma(uy, p.y, ux * p.x));
       const float* f = fj[jl];
+      if constexpr (ROT) {
+        // The start exp(i q_m0 p) in FP64: an FP32 polynomial's error has a
+        // mean common to all atoms, and the walk would turn that constant
+        // into a copy of the amplitude at q = m dq, large at low q.
+        const SinCos z0 = sincos_any(qs[0] * pd);
+        const StepInc d = step_increment(a.dq * pd);
+        const float dr = static_cast<float>(d.cm1), di = static_cast<float>(d.s);
+        float zr = static_cast<float>(z0.c), zi = static_cast<float>(z0.s);
 #pragma unroll
-      for (int m = 0; m < QO; ++m) {
-        const SinCosF e = sincos_qr(qs[m], rp);
-        sre[m] = fmaf(f[m], e.c, sre[m]);
-        sim[m] = fmaf(f[m], e.s, sim[m]);
+        for (int m = 0; m < QO; ++m) {
+          sre[m] = fmaf(f[m], zr, sre[m]);
+          sim[m] = fmaf(f[m], zi, sim[m]);
+          if (m + 1 < QO) {
+            const float nr = fmaf(zr, dr, fmaf(-zi, di, zr));
+            const float ni = fmaf(zr, di, fmaf(zi, dr, zi));
+            zr = nr;
+            zi = ni;
+          }
+        }
+      } else {
+        const double rp = pd * kOneOverPi;
+#pragma unroll
+        for (int m = 0; m < QO; ++m) {
+          const SinCosF e = sincos_qr(qs[m], rp);
+          sre[m] = fmaf(f[m], e.c, sre[m]);
+          sim[m] = fmaf(f[m], e.s, sim[m]);
+        }
       }
     }
 #pragma unroll
@@ -209,7 +262,11 @@ hipError_t launch_geometry(const double4* xyz, int64_t n, double* out, hipStream
 
 hipError_t launch_orient(const OrientArgs& a, int64_t total_blocks, int32_t nq_o, double* I_out, hipStream_t st) {
   if (total_blocks > 0 && nq_o > 0) {
-    hipLaunchKernelGGL(k_orient_amp, dim3(static_cast<uint32_t>(total_blocks), a.parts), dim3(kWave), 0, st, a);
+    const dim3 grid(static_cast<uint32_t>(total_blocks), a.parts);
+    if (a.rot)
+      hipLaunchKernelGGL(k_orient_amp<true>, grid, dim3(kWave), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_orient_amp<false>, grid, dim3(kWave), 0, st, a);
     hipLaunchKernelGGL(k_orient_reduce, dim3(static_cast<uint32_t>(nq_o)), dim3(256), 0, st, a, I_out);
   }
   return hipGetLastError();
