@@ -43,8 +43,16 @@
  *    sas_last_error().  Host-detectable argument errors are reported before
  *    any device work is enqueued and leave the outputs untouched.  Device-side
  *    content errors (a type id outside [0,T), non-finite coordinates) are not
- *    checked: they give unspecified values, never an out-of-bounds access,
- *    because type ids are clamped when the table is read.
+ *    checked by default: they give unspecified values, never an out-of-bounds
+ *    access, because type ids are clamped when the table is read.
+ *  - Debug mode: with the environment variable SAS_DEBUG_VALIDATE set to a
+ *    non-empty value other than "0" when a context is created, every call on
+ *    that context (and every sas_plan_execute of its plans) first checks on
+ *    the device that each type id lies in [0,T) and each coordinate is
+ *    finite, then synchronises the stream and reads the result back: such
+ *    inputs give SAS_ERR_INVALID_ARG, naming the count and the first atom,
+ *    before any output is written.  This mode synchronises (the exception to
+ *    the rule above) and cannot be captured into a graph.
  *  - Thread safety: calls on distinct contexts, plans and workspaces may run
  *    concurrently.  Calls that share a workspace or plan must be ordered on
  *    one stream.

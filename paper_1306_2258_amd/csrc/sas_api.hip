@@ -68,6 +68,10 @@ struct sas_ctx {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
   std::vector<hipEvent_t> ev_pool;
+  // SAS_DEBUG_VALIDATE: check types and coordinates on the device before
+  // each call (a synchronisation each); four counters on the device
+  bool debug_validate = false;
+  unsigned long long* dbg = nullptr;
 };
 
 namespace {
@@ -392,6 +396,27 @@ DescView view_of(const Schedule& sc, const void* ws, const Layout& L) {
   return v;
 }
 
+// Debug mode (SAS_DEBUG_VALIDATE set and not "0" when the context was
+// created): types in [0, T) and finite coordinates, checked on the device,
+// then a synchronisation of the stream.  Without it an out-of-range type is
+// clamped to the nearest valid row and non-finite coordinates give
+// non-finite results.
+sas_status debug_validate(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, int32_t t,
+                          hipStream_t hs) {
+  if (!ctx->debug_validate || n <= 0) return SAS_OK;
+  if (!ctx->dbg) SAS_HIP(hipMalloc(reinterpret_cast<void**>(&ctx->dbg), 4 * sizeof(unsigned long long)));
+  SAS_HIP(hipMemsetAsync(ctx->dbg, 0, 2 * sizeof(unsigned long long), hs));
+  SAS_HIP(hipMemsetAsync(ctx->dbg + 2, 0xff, 2 * sizeof(unsigned long long), hs));
+  SAS_HIP(sas::launch_validate(coords, types, n, t, ctx->dbg, hs));
+  unsigned long long h[4] = {0, 0, 0, 0};
+  SAS_HIP(hipMemcpyAsync(h, ctx->dbg, sizeof(h), hipMemcpyDeviceToHost, hs));
+  SAS_HIP(hipStreamSynchronize(hs));
+  if (h[0])
+    return fail(SAS_ERR_INVALID_ARG, "%llu type ids outside [0, %d), the first at atom %llu", h[0], t, h[2]);
+  if (h[1]) return fail(SAS_ERR_INVALID_ARG, "%llu atoms with a non-finite coordinate, the first at atom %llu", h[1], h[3]);
+  return SAS_OK;
+}
+
 sas_status classify_q(const double* q, int32_t nq, QGrid* g) {
   if (!q) return fail(SAS_ERR_INVALID_ARG, "q is NULL");
   if (nq <= 0 || nq > SAS_MAX_NQ) return fail(SAS_ERR_INVALID_ARG, "q count %d outside [1, %d]", nq, SAS_MAX_NQ);
@@ -550,6 +575,8 @@ sas_status sas_create(int device, sas_ctx** out) {
   if (!c) return fail(SAS_ERR_OUT_OF_MEMORY, "context allocation failed");
   c->device = device;
   c->cu_count = prop.multiProcessorCount;
+  const char* dv = std::getenv("SAS_DEBUG_VALIDATE");
+  c->debug_validate = dv && dv[0] && std::strcmp(dv, "0") != 0;
   *out = c;
   return SAS_OK;
 }
@@ -570,6 +597,7 @@ void sas_destroy(sas_ctx* ctx) {
       (void)hipEventDestroy(ctx->pinned_ev);
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->dbg) (void)hipFree(ctx->dbg);
   }
   delete ctx;
 }
@@ -689,6 +717,8 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, n, t, hs);
+  if (st != SAS_OK) return st;
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
   st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
@@ -743,6 +773,8 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, offsets[S], t, hs);
+  if (st != SAS_OK) return st;
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
   st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
@@ -886,6 +918,12 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
   DeviceGuard g(p->ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", p->ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  {
+    int64_t total = 0;
+    for (int64_t v : p->sizes) total += v;
+    const sas_status sv = debug_validate(p->ctx, p->coords, p->types, total, p->T, hs);
+    if (sv != SAS_OK) return sv;
+  }
   if (!p->ready) {
     // choose the tile shape: forced variant, cached choice, or timing
     int32_t bj = 0, qc = 0;
@@ -961,6 +999,8 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, n, t, hs);
+  if (st != SAS_OK) return st;
   char* w = static_cast<char*>(workspace);
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
@@ -998,6 +1038,8 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, n, t, hs);
+  if (st != SAS_OK) return st;
   char* w = static_cast<char*>(workspace);
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
@@ -1283,6 +1325,8 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, n, t, hs);
+  if (st != SAS_OK) return st;
   char* w = static_cast<char*>(workspace);
 
   // 1. pack (type sort) and geometry; the radius decides the quadrature, so

@@ -127,6 +127,35 @@ __global__ __launch_bounds__(256) void k_pad_table(const float* __restrict__ tab
   tabp[k] = m < Nq ? table[t * Nq + m] : 0.f;
 }
 
+// Input check of the debug mode: flags[0] and flags[1] count atoms with a
+// type id outside [0, T) and atoms with a non-finite coordinate, flags[2] and
+// flags[3] hold the first such atom (the host sets them to all ones).
+__global__ __launch_bounds__(256) void k_validate(const float* __restrict__ coords, const int32_t* __restrict__ types,
+                                                  int64_t n, int32_t T, unsigned long long* __restrict__ flags) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < n; k += stride) {
+    const int32_t ty = types[k];
+    const float x = coords[3 * k], y = coords[3 * k + 1], z = coords[3 * k + 2];
+    if (ty < 0 || ty >= T) {
+      atomicAdd(&flags[0], 1ull);
+      atomicMin(&flags[2], static_cast<unsigned long long>(k));
+    }
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      atomicAdd(&flags[1], 1ull);
+      atomicMin(&flags[3], static_cast<unsigned long long>(k));
+    }
+  }
+}
+
+hipError_t launch_validate(const float* coords, const int32_t* types, int64_t n, int32_t T, unsigned long long* flags,
+                           hipStream_t st) {
+  if (n > 0) {
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, int64_t(256)), 2048);
+    hipLaunchKernelGGL(k_validate, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st, coords, types, n, T, flags);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st) {
   const int64_t total = static_cast<int64_t>(T) * ldt;
   hipLaunchKernelGGL(k_pad_table, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, st, table, T, Nq,

@@ -86,6 +86,8 @@ hipError_t launch_pack(const float* coords, const int32_t* types, const DescView
                        int64_t n_pack_blocks, int32_t T, int32_t* bcount, int32_t* toff, double4* xyz,
                        int32_t* tsort, int32_t* perm, hipStream_t st);
 hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st);
+hipError_t launch_validate(const float* coords, const int32_t* types, int64_t n, int32_t T, unsigned long long* flags,
+                           hipStream_t st);
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
 // Diagonal and q = 0 terms come from the type counts toff (type-segment form)
 // or, when asum is non-null, from the per-block sums of f and f^2 (per-atom
