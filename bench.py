@@ -234,24 +234,23 @@ def main(argv=None):
                               "kappa_at_max": float(ref[err.argmax(), 2] / ref[err.argmax(), 1])}
         log(f"max rel err vs oracle {err.max():.3e}")
 
-    # end to end from host arrays (the paper's GPU times include transfers):
-    # pageable host-to-device copies of coords, types and table, the profile,
-    # and I back on the host; median of 5
-    e2e = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        c_h = torch.from_numpy(m.coords).to(dev)
-        t_h = torch.from_numpy(m.types).to(dev)
-        f_h = torch.from_numpy(m.table).to(dev)
-        sd.debye_profile(c_h, t_h, f_h, m.q, ctx=ctx).cpu()
-        e2e.append(time.perf_counter() - t1)
-    e2e_s = float(np.median(e2e))
-    result["end_to_end"] = {"ms": e2e_s * 1e3, "pair_q_per_s": work / e2e_s,
-                            "includes": "host-to-device copies of coords, types and table, the profile, "
-                                        "and the copy of I(q) back to the host"}
-
     if not args.no_extras:
+        # end to end from host arrays (the paper's GPU times include transfers):
+        # pageable host-to-device copies of coords, types and table, the profile,
+        # and I back on the host; median of 5
+        e2e = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            c_h = torch.from_numpy(m.coords).to(dev)
+            t_h = torch.from_numpy(m.types).to(dev)
+            f_h = torch.from_numpy(m.table).to(dev)
+            sd.debye_profile(c_h, t_h, f_h, m.q, ctx=ctx).cpu()
+            e2e.append(time.perf_counter() - t1)
+        e2e_s = float(np.median(e2e))
+        result["end_to_end"] = {"ms": e2e_s * 1e3, "pair_q_per_s": work / e2e_s,
+                                "includes": "host-to-device copies of coords, types and table, the profile, "
+                                            "and the copy of I(q) back to the host"}
         try:
             result["batched"] = bench_batched(sd, W, torch, dev)
         except Exception as exc:  # reported, never hides the headline
