@@ -387,8 +387,23 @@ def bench_per_atom(sd, W, torch, dev, ms_types):
     work = pair_q(m.n, m.q)
     bj, qc = ctx.variant()
     log(f"per-atom form (T=N=50,000): {ms:.3f} ms (pair kernel {kern_ms:.3f} ms)")
-    return {"form": ctx.form(), "types": int(m.table.shape[0]), "variant": {"bj": bj, "qc": qc}, "ms": ms,
-            "kernel_ms": kern_ms, "pair_q_per_s": work / (ms / 1e3), "slowdown_vs_type_form": ms / ms_types}
+    out = {"form": ctx.form(), "types": int(m.table.shape[0]), "variant": {"bj": bj, "qc": qc}, "ms": ms,
+           "kernel_ms": kern_ms, "pair_q_per_s": work / (ms / 1e3), "slowdown_vs_type_form": ms / ms_types}
+    # the table gradient with one row per atom: per-atom sums over the whole
+    # square of pairs (twice the profile's pairs), profile returned too
+    w = torch.ones(len(m.q), dtype=torch.float64, device=dev)
+    sd.debye_grad_table(coords, types, table, m.q, w, with_profile=True, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.enable_timing(True)
+    ms_g = _time(lambda: sd.debye_grad_table(coords, types, table, m.q, w, with_profile=True, ctx=ctx), torch)
+    ctx.enable_timing(False)
+    kt = ctx.read_timing()
+    kern_g = kt["forward_ms"] / max(kt["forward_launches"], 1)
+    log(f"per-atom table gradient + profile: {ms_g:.3f} ms (square pair kernel {kern_g:.3f} ms)")
+    out["table_grad"] = {"ms_profile_plus_table_grad": ms_g, "kernel_ms": kern_g,
+                         "square_pair_q_per_s": 2.0 * work / (kern_g / 1e3), "ratio_vs_profile": ms_g / ms}
+    return out
 
 
 def bench_grad_table(sd, torch, dev, coords, types, table, q, ms_profile):

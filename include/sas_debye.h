@@ -80,7 +80,7 @@ typedef enum {
 /* Limits of this version. */
 #define SAS_MAX_TYPES 4096          /* T for sas_debye_grad and the type-sorted form */
 #define SAS_MAX_TABLE_TYPES (1 << 24) /* T for the profile calls (per-atom form above SAS_MAX_TYPES) */
-#define SAS_MAX_TABLE_GRAD_TYPES 64 /* T for sas_debye_grad_table                   */
+#define SAS_MAX_TABLE_GRAD_TYPES 64 /* T up to which sas_debye_grad_table keeps per-type sums */
 #define SAS_MAX_NQ 65536            /* Nq                                          */
 #define SAS_MAX_ATOMS 100000000LL   /* atoms per structure                         */
 
@@ -187,14 +187,22 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
  *     grad_table[t][m] = dL_dI[m] * dI(q_m)/df_t(q_m)
  *                      = dL_dI[m] * 2 sum_{i of type t} sum_j f_j(q_m) sinc(q_m r_ij)
  * (j over all atoms, i included).  It is what fitting form-factor or
- * solvent parameters needs (chain rule through the table).  One pass of the
- * type-sorted forward kernel that also keeps per-type sums: about the cost
- * of a profile.
+ * solvent parameters needs (chain rule through the table).  Two forms:
+ *  - t <= SAS_MAX_TABLE_GRAD_TYPES: one pass of the type-sorted forward
+ *    kernel that also keeps per-type sums, about the cost of a profile;
+ *  - more rows (per-atom form factors, the text below Eq. 2), or the context's
+ *    form set to SAS_FORM_PER_ATOM: the per-atom sums
+ *    S_i = sum_j f_j sinc(q r_ij) over the whole square of pairs (twice the
+ *    profile's pairs), then added by type in atom order after a stable sort
+ *    of the atoms by type.  Rows of types no atom holds are zero.  The
+ *    workspace holds an FP32 [ceil(n/512)][nq][n] array of per-block sums
+ *    (3.8 GiB for n = 50,000 and nq = 200).
+ * Both are deterministic: identical calls give identical bits.
  *   dL_dI          dev double [nq]     weights
  *   grad_table_out dev double [t][nq]  written
  *   I_out          dev double [nq] or NULL: if given, the profile is written too
  * q: any increasing grid (uniform: recurrence; otherwise direct).
- * 1 <= t <= SAS_MAX_TABLE_GRAD_TYPES (SAS_ERR_UNSUPPORTED otherwise).
+ * 1 <= t <= SAS_MAX_TABLE_TYPES.
  * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 2).
  */
 sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,

@@ -318,7 +318,9 @@ def debye_profile_hybrid(coords: torch.Tensor, types: torch.Tensor, table: torch
 def debye_grad_table(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, dL_dI: torch.Tensor, *,
                      with_profile: bool = False, ctx: Optional[Context] = None):
     """dL_dI[m] dI(q_m)/dtable[t][m] as float64 [T, Nq] (and the profile if
-    ``with_profile``); T <= 64."""
+    ``with_profile``).  Up to 64 rows the forward pass keeps per-type sums;
+    beyond (per-atom form factors), or with the context's form set to
+    'per_atom', per-atom sums over all pairs are added by type."""
     _check_inputs(coords, types, table)
     ctx = ctx or default_context(coords.device)
     qh = _q_host(q)

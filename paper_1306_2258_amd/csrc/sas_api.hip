@@ -528,6 +528,126 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   return SAS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Table gradient with many table rows (per-atom form factors): per-atom sums
+// over the whole square of pairs, then per type.
+// ---------------------------------------------------------------------------
+int64_t ceil_div64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool table_grad_by_atom(const sas_ctx* ctx, int32_t T) {
+  return T > SAS_MAX_TABLE_GRAD_TYPES || (ctx && ctx->force_per_atom);
+}
+
+struct RowsLayout {
+  Schedule sc;
+  int32_t nJ = 0, end_bit = 1;
+  size_t xyz = 0, tsort = 0, perm = 0, asum = 0, upload = 0, upload_bytes = 0, tabp = 0, rows = 0, srow = 0;
+  size_t keys = 0, atoms = 0, f0 = 0, tmp = 0, tmp_bytes = 0, total = 0;
+};
+
+// J blocks of at most 512 atoms (the FP32 sum of one block is exact enough,
+// as in the forward), smaller for small structures so that the square still
+// holds about 2048 work-groups.
+RowsLayout rows_layout(const sas_ctx* ctx, int64_t n, int32_t T, int32_t Nq, bool direct) {
+  RowsLayout R;
+  R.sc = make_schedule(ctx, std::vector<int64_t>{n}, T, Nq, 0, 0, direct, true);
+  const int64_t nI = std::max<int64_t>(1, ceil_div64(n, sas::kWave));
+  int64_t bj = ceil_div64(n, std::max<int64_t>(1, ceil_div64(2048, nI)));
+  bj = std::min<int64_t>(512, std::max<int64_t>(sas::kWave, ceil_div64(bj, sas::kWave) * sas::kWave));
+  R.sc.geo.bj = static_cast<int32_t>(bj);
+  R.sc.geo.c = R.sc.geo.bj / sas::kWave;
+  R.sc.geo.g = 1;
+  R.nJ = static_cast<int32_t>(std::max<int64_t>(1, ceil_div64(n, bj)));
+  while (R.end_bit < 31 && (int64_t(1) << R.end_bit) < T) ++R.end_bit;
+  size_t p = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = p;
+    p = align_up(p + std::max<size_t>(bytes, 1));
+    return at;
+  };
+  R.xyz = take(sizeof(double4) * n);
+  R.tsort = take(sizeof(int32_t) * n);
+  R.perm = take(sizeof(int32_t) * n);
+  R.asum = take(sizeof(double) * 2 * R.sc.n_pack * static_cast<size_t>(Nq));
+  R.upload_bytes = direct ? sizeof(double) * static_cast<size_t>(Nq) : 0;
+  R.upload = take(R.upload_bytes);
+  R.tabp = take(sizeof(float) * static_cast<size_t>(T) * R.sc.ldt);
+  R.rows = take(sizeof(float) * static_cast<size_t>(R.nJ) * Nq * n);
+  R.srow = take(sizeof(double) * static_cast<size_t>(Nq) * n);
+  R.keys = take(sizeof(int32_t) * n);
+  R.atoms = take(sizeof(int32_t) * n);
+  R.f0 = take(sizeof(double));
+  size_t tb = 0;
+  if (n > 0 && sas::sort_atoms_by_type(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, static_cast<int32_t>(n),
+                                       R.end_bit, nullptr) != hipSuccess)
+    tb = 0;
+  R.tmp_bytes = tb;
+  R.tmp = take(tb);
+  R.total = p;
+  return R;
+}
+
+sas_status enqueue_table_grad_by_atom(sas_ctx* ctx, const RowsLayout& R, const float* coords, const int32_t* types,
+                                      int64_t n, const float* table, int32_t T, int32_t Nq, const QGrid& grid,
+                                      const double* w, double* grad_table, double* I_out, void* ws, hipStream_t st) {
+  char* b = static_cast<char*>(ws);
+  const Schedule& sc = R.sc;
+  auto* xyz = reinterpret_cast<double4*>(b + R.xyz);
+  auto* tsort = reinterpret_cast<int32_t*>(b + R.tsort);
+  auto* perm = reinterpret_cast<int32_t*>(b + R.perm);
+  auto* asum = reinterpret_cast<double*>(b + R.asum);
+  auto* tabp = reinterpret_cast<float*>(b + R.tabp);
+  auto* rows = reinterpret_cast<float*>(b + R.rows);
+  auto* srow = reinterpret_cast<double*>(b + R.srow);
+  auto* keys = reinterpret_cast<int32_t*>(b + R.keys);
+  auto* atoms = reinterpret_cast<int32_t*>(b + R.atoms);
+  auto* f0 = reinterpret_cast<double*>(b + R.f0);
+  const double* qdev = sc.direct ? reinterpret_cast<const double*>(b + R.upload) : nullptr;
+  if (sc.direct) {
+    std::vector<char> img(R.upload_bytes);
+    std::memcpy(img.data(), grid.host, R.upload_bytes);
+    const sas_status s2 = stage_upload_to(ctx, b + R.upload, img, st);
+    if (s2 != SAS_OK) return s2;
+  }
+  DescView sd;
+  std::memset(&sd, 0, sizeof(sd));
+  sd.S = 1;
+  sd.one = sc.desc[0];
+  SAS_HIP(sas::launch_pad_table(table, T, Nq, sc.ldt, tabp, st));
+  SAS_HIP(sas::launch_pack_plain(coords, types, n, T, xyz, tsort, perm, st));
+  SAS_HIP(sas::launch_atom_sums(sd, sc.n_pack, tsort, tabp, T, sc.ldt, Nq, asum, st));
+  sas::ForwardArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.sd = sd;
+  a.geo = sc.geo;
+  a.xyz = xyz;
+  a.tsort = tsort;
+  a.tabp = tabp;
+  a.ldt = sc.ldt;
+  a.T = T;
+  a.Nq = Nq;
+  a.qc = sc.qc;
+  a.q0 = grid.q0;
+  a.dq = grid.dq;
+  a.qdev = qdev;
+  a.rows = rows;
+  a.rows_ld = Nq;
+  {
+    LaunchTimer timer(ctx, st, false);
+    SAS_HIP(sas::launch_forward_pa_rows(a, sc.qc_template, st));
+  }
+  SAS_HIP(sas::launch_rows_f0(asum, sc.n_pack, Nq, f0, st));
+  SAS_HIP(sas::launch_rows_final(rows, R.nJ, Nq, static_cast<int32_t>(n), Nq, tabp, sc.ldt, tsort, grid.q0, grid.dq,
+                                 qdev, f0, srow, st));
+  if (I_out) SAS_HIP(sas::launch_rows_profile(srow, tabp, sc.ldt, tsort, static_cast<int32_t>(n), Nq, I_out, st));
+  if (n > 0) {
+    size_t tb = R.tmp_bytes;
+    SAS_HIP(sas::sort_atoms_by_type(b + R.tmp, &tb, tsort, keys, perm, atoms, static_cast<int32_t>(n), R.end_bit, st));
+  }
+  SAS_HIP(sas::launch_rows_by_type(keys, atoms, static_cast<int32_t>(n), srow, T, Nq, w, grad_table, st));
+  return SAS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -669,13 +789,15 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 }
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
-  const int32_t max_t = grad == 2 ? SAS_MAX_TABLE_GRAD_TYPES : (grad ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES);
+  const int32_t max_t = grad == 1 ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES;
   if (check_sizes(n, t, nq, max_t) != SAS_OK) return 0;
   const std::vector<int64_t> sizes{n};
   if (grad == 2) {
     size_t need = 0;
     for (bool direct : {false, true})
-      need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, direct, false, t), t, nq).total);
+      need = std::max(need, table_grad_by_atom(ctx, t)
+                                ? rows_layout(ctx, n, t, nq, direct).total
+                                : make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, direct, false, t), t, nq).total);
     return need;
   }
   if (grad) {
@@ -983,13 +1105,28 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
                                 const float* table, int32_t t, const double* q, int32_t nq, const double* dL_dI,
                                 double* grad_table_out, double* I_out, void* workspace, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  sas_status st = check_sizes(n, t, nq, SAS_MAX_TABLE_GRAD_TYPES);
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TABLE_TYPES);
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
   if (!table || !dL_dI || !grad_table_out) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI/grad_table_out is NULL");
   QGrid grid;
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
+  if (table_grad_by_atom(ctx, t)) {
+    const RowsLayout R = rows_layout(ctx, n, t, nq, !grid.uniform || ctx->force_direct);
+    if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+      return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (ws_bytes < R.total) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, R.total);
+    if (n > 0 && R.tmp_bytes == 0) return fail(SAS_ERR_HIP, "radix sort size query failed");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    st = debug_validate(ctx, coords, types, n, t, hs);
+    if (st != SAS_OK) return st;
+    return enqueue_table_grad_by_atom(ctx, R, coords, types, n, table, t, nq, grid, dL_dI, grad_table_out, I_out,
+                                      workspace, hs);
+  }
   const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform, false, t);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");

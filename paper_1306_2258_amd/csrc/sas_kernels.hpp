@@ -56,6 +56,8 @@ struct ForwardArgs {
   double q0, dq;        // uniform grid q_m = q0 + m dq (recurrence form)
   const double* qdev;   // non-null: arbitrary grid [Nq] on the device (direct form)
   double* gpart;        // table gradient only: [strips][T][Nq] per-type sums
+  float* rows;          // per-atom table gradient: [J blocks][rows_ld][n] per-atom sums
+  int32_t rows_ld;      // q stride of rows (>= Nq)
 };
 
 constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
@@ -152,6 +154,23 @@ hipError_t launch_pack_plain(const float* coords, const int32_t* types, int64_t 
 hipError_t launch_atom_sums(const DescView& sd, int64_t n_pack_blocks, const int32_t* tsort, const float* tabp,
                             int32_t T, int32_t ldt, int32_t Nq, double* asum, hipStream_t st);
 hipError_t launch_forward_pa(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);
+// Per-atom sums over the whole square (one structure): ROWS variant above.
+hipError_t launch_forward_pa_rows(const ForwardArgs& a, int32_t qc_template, hipStream_t st);
+// Per-atom table gradient from the rows: sum of f(0) over all atoms; the
+// per-atom sums S_i(q_m) = f_i + R_i / q_m ([Nq][n]); the profile from them;
+// the stable sort of atoms by type (hipCUB radix sort; *tmp_bytes is the
+// temporary size, queried with tmp = NULL); the per-type sums times 2 w_m.
+hipError_t launch_rows_f0(const double* asum, int64_t n_pack, int32_t Nq, double* f0, hipStream_t st);
+hipError_t launch_rows_final(const float* rows, int32_t nJ, int32_t rows_ld, int32_t n, int32_t Nq, const float* tabp,
+                             int32_t ldt,
+                             const int32_t* tsort, double q0, double dq, const double* qdev, const double* f0,
+                             double* srow, hipStream_t st);
+hipError_t launch_rows_profile(const double* srow, const float* tabp, int32_t ldt, const int32_t* tsort, int32_t n,
+                               int32_t Nq, double* I_out, hipStream_t st);
+hipError_t sort_atoms_by_type(void* tmp, size_t* tmp_bytes, const int32_t* keys_in, int32_t* keys_out,
+                              const int32_t* vals_in, int32_t* vals_out, int32_t n, int32_t end_bit, hipStream_t st);
+hipError_t launch_rows_by_type(const int32_t* keys, const int32_t* atoms, int32_t n, const double* srow, int32_t T,
+                               int32_t Nq, const double* w, double* grad_table, hipStream_t st);
 bool pa_qc_supported(int32_t qc);
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st);

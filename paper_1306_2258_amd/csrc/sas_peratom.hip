@@ -17,6 +17,14 @@
 //            and added to FP64 strip totals.
 // The strip schedule, the q recurrence (or the direct sine) and the reduce are
 // the type-segment form's.
+//
+// With ROWS the same pair loop serves the derivative with respect to the
+// form factors: each lane keeps its own atom's sum R_i(q_m) = sum over j != i
+// of f_j(q_m) sin(q_m r_ij) / r_ij instead of reducing over the lanes.  The
+// grid then covers the whole square of (I block, J block) pairs, one J block
+// per work-group, and each lane stores its FP32 sums for the J block as one
+// column of rows[J][q][atom] (atom index fastest, so the 64 lanes store 64
+// consecutive values per q); the J blocks are added in FP64 afterwards.
 #include <hip/hip_runtime.h>
 
 #include "sas_device.hpp"
@@ -72,7 +80,8 @@ __global__ __launch_bounds__(256) void k_atom_sums(DescView sd, const int32_t* _
   }
 }
 
-template <int QC, bool DIRECT>
+
+template <int QC, bool DIRECT, bool ROWS>
 __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forward_pa(ForwardArgs a) {
   constexpr int NG = QC / kWave;
   constexpr int R = QC % kWave;
@@ -86,9 +95,18 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
   __shared__ double qv[DIRECT ? QC : 1];
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
-  const int s = find_struct_by_strip(a.sd, t);
+  const int s = ROWS ? 0 : find_struct_by_strip(a.sd, t);
   const StructDesc d = a.sd.get(s);
-  const StripPos sp = decode_strip(t - d.strip_off, d.n, a.geo);
+  StripPos sp;
+  if constexpr (ROWS) {
+    // square schedule: I block t / nJ with J block t % nJ
+    const int nJ = static_cast<int>(ceil_div(d.n, a.geo.bj));
+    sp.I = static_cast<int32_t>(t / nJ);
+    sp.Ja = static_cast<int32_t>(t - static_cast<int64_t>(sp.I) * nJ);
+    sp.Jb = sp.Ja + 1;
+  } else {
+    sp = decode_strip(t - d.strip_off, d.n, a.geo);
+  }
   const int n = d.n;
   const int i = sp.I * kWave + lane;
   const bool vi = i < n;
@@ -157,7 +175,7 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
           const double ir = rsqrt_f64(r2);
           const double rp = r2 * ir * kOneOverPi;
-          const float w = (vi && jl > i) ? static_cast<float>(ir) : 0.f;
+          const float w = (vi && (ROWS ? jl != i : jl > i)) ? static_cast<float>(ir) : 0.f;
           const float* fb = fj[jl - u0];
 #pragma unroll
           for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w * fb[m], acc[m]);
@@ -169,9 +187,9 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
         for (int jl = u0; jl < u0 + ns; jl += 2) {
           const bool two = jl + 1 < u0 + ns;
           const int jb = two ? jl + 1 : jl;
-          const PairSeed A = pair_seed(pi, sj[jl - u0], vi && jl > i, dq, qs);
+          const PairSeed A = pair_seed(pi, sj[jl - u0], vi && (ROWS ? jl != i : jl > i), dq, qs);
           asm volatile("" ::: "memory");
-          const PairSeed B = pair_seed(pi, sj[jb - u0], vi && jb > i && two, dq, qs);
+          const PairSeed B = pair_seed(pi, sj[jb - u0], vi && (ROWS ? jb != i : jb > i) && two, dq, qs);
           asm volatile("" ::: "memory");
           const float* fa = fj[jl - u0];
           const float* fb = fj[jb - u0];
@@ -193,6 +211,19 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
         }
       }
     }
+    if constexpr (ROWS) {
+      // (only this chunk's nqc values: the steps past them belong to the next
+      // chunk, which stores its own)
+      if (vi) {
+        float* p = a.rows + (static_cast<int64_t>(J) * a.rows_ld + m0) * n + i;
+#pragma unroll
+        for (int m = 0; m < QC; ++m) {
+          if (m < nqc) *p = acc[m];
+          p += n;
+        }
+      }
+      continue;
+    }
     // weight by this lane's f_i(q_m), sum over lanes, add in FP64 (the row
     // pointer is laundered so that the loads are not hoisted into registers)
     const float* far = fa_row;
@@ -209,11 +240,13 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
       tot[NG][lane] += static_cast<double>(v);
     }
   }
-  double* out = a.partial + t * a.Nq + m0;
+  if constexpr (!ROWS) {
+    double* out = a.partial + t * a.Nq + m0;
 #pragma unroll
-  for (int g = 0; g < NT; ++g) {
-    const int m = g * kWave + lane;
-    if (m < nqc) out[m] = tot[g][lane];
+    for (int g = 0; g < NT; ++g) {
+      const int m = g * kWave + lane;
+      if (m < nqc) out[m] = tot[g][lane];
+    }
   }
 }
 
@@ -239,25 +272,37 @@ hipError_t launch_atom_sums(const DescView& sd, int64_t n_pack_blocks, const int
   return hipGetLastError();
 }
 
-hipError_t launch_forward_pa(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st) {
-  if (n_strips_total <= 0) return hipSuccess;
-  const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
-  const dim3 grid(static_cast<uint32_t>(n_strips_total), nchunks);
+template <bool ROWS>
+hipError_t launch_forward_pa_t(const ForwardArgs& a, dim3 grid, int32_t qc_template, hipStream_t st) {
   if (a.qdev) {
     if (qc_template != 32) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_forward_pa<32, true>), grid, dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL((k_forward_pa<32, true, ROWS>), grid, dim3(kWave), 0, st, a);
     return hipGetLastError();
   }
   switch (qc_template) {
-    case 16: hipLaunchKernelGGL((k_forward_pa<16, false>), grid, dim3(kWave), 0, st, a); break;
-    case 32: hipLaunchKernelGGL((k_forward_pa<32, false>), grid, dim3(kWave), 0, st, a); break;
-    case 64: hipLaunchKernelGGL((k_forward_pa<64, false>), grid, dim3(kWave), 0, st, a); break;
-    case 100: hipLaunchKernelGGL((k_forward_pa<100, false>), grid, dim3(kWave), 0, st, a); break;
-    case 128: hipLaunchKernelGGL((k_forward_pa<128, false>), grid, dim3(kWave), 0, st, a); break;
-    case 200: hipLaunchKernelGGL((k_forward_pa<200, false>), grid, dim3(kWave), 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_forward_pa<16, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
+    case 32: hipLaunchKernelGGL((k_forward_pa<32, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_forward_pa<64, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
+    case 100: hipLaunchKernelGGL((k_forward_pa<100, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_forward_pa<128, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
+    case 200: hipLaunchKernelGGL((k_forward_pa<200, false, ROWS>), grid, dim3(kWave), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_forward_pa(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st) {
+  if (n_strips_total <= 0) return hipSuccess;
+  const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
+  return launch_forward_pa_t<false>(a, dim3(static_cast<uint32_t>(n_strips_total), nchunks), qc_template, st);
+}
+
+hipError_t launch_forward_pa_rows(const ForwardArgs& a, int32_t qc_template, hipStream_t st) {
+  const StructDesc d = a.sd.one;
+  if (d.n <= 0) return hipSuccess;
+  const int64_t blocks = ceil_div(d.n, kWave) * ceil_div(d.n, a.geo.bj);
+  const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
+  return launch_forward_pa_t<true>(a, dim3(static_cast<uint32_t>(blocks), nchunks), qc_template, st);
 }
 
 }  // namespace sas

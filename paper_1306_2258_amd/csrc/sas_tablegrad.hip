@@ -8,7 +8,25 @@
 // TG = true (sas_forward_kernel.hpp) accumulates G per strip beside the
 // profile's partial rows; the strips are then summed in a fixed order and
 // the final step forms w_m dI/df_t(q_m) for the caller's weights w.
+//
+// With many table rows (per-atom form factors) per-type sums in the forward
+// pass would need T rows per strip.  That form instead takes, for every atom,
+// S_i(q_m) = sum over all j of f_j(q_m) sinc(q_m r_ij) (the j = i term is
+// f_i), since dI/df_t = 2 sum over atoms i of type t of S_i:
+//   rows     the per-atom forward pass over the whole square of pairs
+//            (k_forward_pa with ROWS), R_i = sum_{j != i} f_j sin(q r)/r per
+//            J block, in FP32;
+//   final    S_i = f_i + R_i / q_m (J blocks summed in FP64, in order); at q_m = 0,
+//            S_i = sum_j f_j(0);
+//   profile  I(q_m) = sum_i f_i S_i, one work-group per q, fixed order;
+//   by type  atoms sorted by type (stable radix sort, so each type's atoms
+//            stay in index order), then one thread per (type, q) sums its
+//            atoms' S_i in that order and writes 2 w_m times the sum.
 #include <hip/hip_runtime.h>
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
 
 #include "sas_forward_kernel.hpp"
 #include "sas_kernels.hpp"
@@ -73,6 +91,123 @@ hipError_t launch_table_grad_final(int64_t n_slices, const double* gslices, cons
   const int64_t total = static_cast<int64_t>(T) * Nq;
   hipLaunchKernelGGL(k_table_grad_final, dim3(static_cast<uint32_t>(ceil_div(total, 256))), dim3(256), 0, st,
                      n_slices, gslices, toff, table, T, Nq, q0, dq, qdev, w, grad_table);
+  return hipGetLastError();
+}
+
+__global__ void k_rows_f0(const double* __restrict__ asum, int64_t n_pack, int32_t Nq, double* __restrict__ f0) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < n_pack; ++b) s += asum[(b * 2 + 0) * Nq];
+  f0[0] = s;
+}
+
+hipError_t launch_rows_f0(const double* asum, int64_t n_pack, int32_t Nq, double* f0, hipStream_t st) {
+  hipLaunchKernelGGL(k_rows_f0, dim3(1), dim3(64), 0, st, asum, n_pack, Nq, f0);
+  return hipGetLastError();
+}
+
+// Grid-stride over (q, atom) with the atom fastest.
+__global__ __launch_bounds__(256) void k_rows_final(const float* __restrict__ rows, int32_t nJ, int32_t rows_ld,
+                                                    int32_t n, int32_t Nq, const float* __restrict__ tabp, int32_t ldt,
+                                                    const int32_t* __restrict__ tsort, double q0, double dq,
+                                                    const double* __restrict__ qdev, const double* __restrict__ f0,
+                                                    double* __restrict__ srow) {
+  const int64_t total = static_cast<int64_t>(n) * Nq;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
+    const int m = static_cast<int>(k / n);
+    const int64_t i = k - static_cast<int64_t>(m) * n;
+    const double qm = qdev ? qdev[m] : q0 + m * dq;
+    double v;
+    if (qm == 0.0) {
+      v = f0[0];
+    } else {
+      double r = 0.0;
+      for (int J = 0; J < nJ; ++J) r += static_cast<double>(rows[(static_cast<int64_t>(J) * rows_ld + m) * n + i]);
+      v = static_cast<double>(tabp[static_cast<int64_t>(tsort[i]) * ldt + m]) + r / qm;
+    }
+    srow[k] = v;
+  }
+}
+
+int64_t grid_stride_blocks(int64_t total) { return std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 65536)); }
+
+hipError_t launch_rows_final(const float* rows, int32_t nJ, int32_t rows_ld, int32_t n, int32_t Nq, const float* tabp,
+                             int32_t ldt, const int32_t* tsort, double q0, double dq, const double* qdev,
+                             const double* f0, double* srow, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = grid_stride_blocks(static_cast<int64_t>(n) * Nq);
+  hipLaunchKernelGGL(k_rows_final, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st, rows, nJ, rows_ld, n, Nq,
+                     tabp, ldt, tsort, q0, dq, qdev, f0, srow);
+  return hipGetLastError();
+}
+
+// One work-group per q: sum_i f_i S_i, threads strided over the atoms, then a
+// fixed tree.
+__global__ __launch_bounds__(256) void k_rows_profile(const double* __restrict__ srow, const float* __restrict__ tabp,
+                                                      int32_t ldt, const int32_t* __restrict__ tsort, int32_t n,
+                                                      int32_t Nq, double* __restrict__ I_out) {
+  __shared__ double red[256];
+  const int m = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    acc = fma(static_cast<double>(tabp[static_cast<int64_t>(tsort[i]) * ldt + m]), srow[static_cast<int64_t>(m) * n + i],
+              acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) I_out[m] = red[0];
+}
+
+hipError_t launch_rows_profile(const double* srow, const float* tabp, int32_t ldt, const int32_t* tsort, int32_t n,
+                               int32_t Nq, double* I_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_rows_profile, dim3(static_cast<uint32_t>(Nq)), dim3(256), 0, st, srow, tabp, ldt, tsort, n, Nq,
+                     I_out);
+  return hipGetLastError();
+}
+
+hipError_t sort_atoms_by_type(void* tmp, size_t* tmp_bytes, const int32_t* keys_in, int32_t* keys_out,
+                              const int32_t* vals_in, int32_t* vals_out, int32_t n, int32_t end_bit, hipStream_t st) {
+  return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, keys_in, keys_out, vals_in, vals_out, n, 0, end_bit, st);
+}
+
+// Grid-stride over (q, sorted position k): the first atom of each type's run
+// sums the run's S_i in order.  Rows of types no atom holds are zero.
+__global__ __launch_bounds__(256) void k_rows_by_type(const int32_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ atoms, int32_t n,
+                                                      const double* __restrict__ srow, int32_t Nq,
+                                                      const double* __restrict__ w, double* __restrict__ grad_table) {
+  const int64_t total = static_cast<int64_t>(n) * Nq;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int m = static_cast<int>(idx / n);
+    const int64_t k = idx - static_cast<int64_t>(m) * n;
+    const int32_t t = keys[k];
+    if (k > 0 && keys[k - 1] == t) continue;
+    double s = 0.0;
+    for (int64_t e = k; e < n && keys[e] == t; ++e) s += srow[static_cast<int64_t>(m) * n + atoms[e]];
+    grad_table[static_cast<int64_t>(t) * Nq + m] = 2.0 * w[m] * s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, int64_t count) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count; k += stride) p[k] = 0.0;
+}
+
+hipError_t launch_rows_by_type(const int32_t* keys, const int32_t* atoms, int32_t n, const double* srow, int32_t T,
+                               int32_t Nq, const double* w, double* grad_table, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(T) * Nq;
+  hipLaunchKernelGGL(k_fill_zero, dim3(static_cast<uint32_t>(grid_stride_blocks(total))), dim3(256), 0, st, grad_table,
+                     total);
+  if (n > 0) {
+    const int64_t blocks = grid_stride_blocks(static_cast<int64_t>(n) * Nq);
+    hipLaunchKernelGGL(k_rows_by_type, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st, keys, atoms, n, srow, Nq,
+                       w, grad_table);
+  }
   return hipGetLastError();
 }
 

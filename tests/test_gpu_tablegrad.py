@@ -121,15 +121,12 @@ def test_table_grad_coincident_atoms(sd):
     check(sd, m, np.random.default_rng(2).normal(size=len(m.q)))
 
 
-def test_table_grad_limits(sd):
-    import torch
-
-    say("table gradient refuses T > 64")
-    m = W.random_molecule(1380, 100, 10, t=65, q0=0.0, q1=0.5, extent=10.0)
-    c, t, tab = to_dev(m)
-    with pytest.raises(sd.SasError) as e:
-        sd.debye_grad_table(c, t, tab, m.q, torch.ones(10, dtype=torch.float64, device="cuda"))
-    assert e.value.status == 3
+def test_table_grad_many_types(sd):
+    """T = 65 is past the per-type sums of the forward pass: the per-atom
+    form takes over, same results."""
+    say("table gradient T=65 (per-atom form)")
+    m = W.random_molecule(1380, 400, 20, t=65, q0=0.0, q1=0.5, extent=14.0, widths=np.linspace(0.2, 1.5, 65))
+    check(sd, m, np.random.default_rng(6).normal(size=len(m.q)))
 
 
 def test_table_grad_autograd(sd):

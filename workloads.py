@@ -332,6 +332,18 @@ def with_per_atom_factors(m: Molecule, seed: int, spread: float = 0.1, shuffle: 
                     dict(m.extra))
 
 
+def with_random_rows(m: Molecule, t: int, seed: int) -> Molecule:
+    """The same atoms with t table rows Z_r exp(-B_r q^2), Z_r ~ U(1, 16) and
+    B_r ~ U(0.2, 1.5) (not separable), each atom's row drawn uniformly: with t
+    comparable to the atom count some rows are shared and some unused."""
+    rng = rng_for(seed)
+    rows = rng.integers(0, t, size=m.n).astype(np.int32)
+    z = rng.uniform(1.0, 16.0, size=t)
+    b = rng.uniform(0.2, 1.5, size=t)
+    table = (z[:, None] * np.exp(-b[:, None] * m.q[None, :] ** 2)).astype(np.float32)
+    return Molecule(m.name + f"_rows{t}", m.coords, rows, table, m.q, dict(m.extra))
+
+
 WORKLOADS = {
     "ellipsoid_1k": ellipsoid_1k,
     "globular_10k": globular_10k,
