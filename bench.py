@@ -403,6 +403,19 @@ def bench_per_atom(sd, W, torch, dev, ms_types):
     log(f"per-atom table gradient + profile: {ms_g:.3f} ms (square pair kernel {kern_g:.3f} ms)")
     out["table_grad"] = {"ms_profile_plus_table_grad": ms_g, "kernel_ms": kern_g,
                          "square_pair_q_per_s": 2.0 * work / (kern_g / 1e3), "ratio_vs_profile": ms_g / ms}
+    # the coordinate gradient with one row per atom (per-atom adjoint), the
+    # profile returned too
+    sd.debye_grad(coords, types, table, m.q, w, with_profile=True, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.read_timing()
+    ctx.enable_timing(True)
+    ms_c = _time(lambda: sd.debye_grad(coords, types, table, m.q, w, with_profile=True, ctx=ctx), torch)
+    ctx.enable_timing(False)
+    kt = ctx.read_timing()
+    adj_ms = kt["adjoint_ms"] / max(kt["adjoint_launches"], 1)
+    log(f"per-atom coordinate gradient + profile: {ms_c:.3f} ms (adjoint kernel {adj_ms:.3f} ms)")
+    out["coord_grad"] = {"ms_profile_plus_grad": ms_c, "adjoint_kernel_ms": adj_ms,
+                         "adjoint_pair_q_per_s": work / (adj_ms / 1e3), "ratio_vs_profile": ms_c / ms}
     return out
 
 

@@ -78,7 +78,7 @@ typedef enum {
 } sas_status;
 
 /* Limits of this version. */
-#define SAS_MAX_TYPES 4096          /* T for sas_debye_grad and the type-sorted form */
+#define SAS_MAX_TYPES 4096          /* T up to which the type-sorted form can be used  */
 #define SAS_MAX_TABLE_TYPES (1 << 24) /* T for the profile calls (per-atom form above SAS_MAX_TYPES) */
 #define SAS_MAX_TABLE_GRAD_TYPES 64 /* T up to which sas_debye_grad_table keeps per-type sums */
 #define SAS_MAX_NQ 65536            /* Nq                                          */
@@ -173,8 +173,12 @@ void sas_plan_destroy(sas_plan* plan);
  *   I_out    dev double [nq] or NULL: if given, the profile is written too
  * q follows the profile's conventions: a uniform grid takes the recurrence,
  * any other increasing grid the direct variant (sin and cos of q r evaluated
- * for every pair and q, about four times the cost).  t <= SAS_MAX_TYPES
- * (SAS_ERR_UNSUPPORTED otherwise).
+ * for every pair and q, about four times the cost).  The table form follows
+ * the profile's choice: the type-sorted form, or with many rows (per-atom
+ * form factors: t > SAS_MAX_TYPES, or t >= 64 with fewer than 16 atoms per
+ * row) or SAS_FORM_PER_ATOM the per-atom form, whose pair weights
+ * dL_dI[m] f_i(q_m) f_j(q_m) are formed inside the q loop.
+ * 1 <= t <= SAS_MAX_TABLE_TYPES.
  * workspace >= sas_debye_workspace_size(ctx, n, t, nq, 1).
  */
 sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, const float* table,

@@ -25,6 +25,15 @@
 // cos of q_m r for every q (FP64 reduction of q r / pi, FP32 polynomials, as
 // in the forward's direct form) and accumulates C and S with their signs,
 // two FMAs per atom and q.
+//
+// Per-atom form factors (k_adjoint_pa: many table rows, no type sort): U_m
+// is a product of the pair's own rows, U_m = (w_m f_i(q_m)) f_j(q_m).  Each
+// lane holds w_m f_i for a chunk of up to 100 q values in registers, 1/q_m is
+// read from LDS (the same address in every lane), and the J atoms' rows are
+// staged in LDS in runs of kPaSub beside their positions, as in the
+// per-atom forward; so a q step costs two FP32 products (U and V = U/q) more
+// than the type form.  One atom per lane, and the same strip rows and final
+// reduce as the type form.
 #include <hip/hip_runtime.h>
 
 #include "sas_device.hpp"
@@ -316,6 +325,143 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   outi[3 * (lane + kWave) + 2] = g2z;
 }
 
+template <int QA, bool DIRECT>
+__global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
+  static_assert(QA % 4 == 0, "table rows are staged as float4");
+  constexpr int BJ = kAdjPaBJ;
+  constexpr int Q4 = QA / 4;
+  constexpr int E4 = kPaSub * Q4;  // float4 elements of one run's rows
+  __shared__ double4 sj[kPaSub];
+  __shared__ __align__(16) float fj[kPaSub][QA];
+  __shared__ double gjl[BJ * 3];
+  __shared__ __align__(16) float iql[QA];
+  __shared__ double qvl[DIRECT ? QA : 1];
+
+  const int lane = threadIdx.x;
+  const int64_t t = blockIdx.x;
+  const StructDesc d = a.sd.get(0);
+  const StripPos sp = decode_strip(t, d.n, a.geo);
+  const int n = d.n;
+  const int i = sp.I * kWave + lane;
+  const bool vi = i < n;
+  const int ic = vi ? i : n - 1;
+  const double4 pi = a.xyz[d.atom_off + ic];
+  const int ti = clamp_type(a.tsort[d.atom_off + ic], a.T);
+
+  const int m0 = blockIdx.y * a.qa;
+  const int nqa = min(a.qa, a.Nq - m0);  // <= QA
+  const double qs = a.q0 + m0 * a.dq;
+  const double dq = a.dq;
+  const int64_t pidx = static_cast<int64_t>(blockIdx.y) * a.n_strips + t;
+  // this lane's weights w_m f_i(q_m) (zero at q = 0, where I does not depend
+  // on the positions, and past the chunk) and the chunk's 1/q_m
+  float wi[QA];
+  const float* fi = a.tabp + static_cast<int64_t>(ti) * a.ldt + m0;
+#pragma unroll
+  for (int m = 0; m < QA; ++m) {
+    const double qm = m < nqa ? (DIRECT ? a.qdev[m0 + m] : a.q0 + (m0 + m) * dq) : 0.0;
+    wi[m] = qm > 0.0 ? static_cast<float>(a.w[m0 + m] * static_cast<double>(fi[m])) : 0.f;
+  }
+  for (int m = lane; m < QA; m += kWave) {
+    const double qm = m < nqa ? (DIRECT ? a.qdev[m0 + m] : a.q0 + (m0 + m) * dq) : 0.0;
+    iql[m] = qm > 0.0 ? static_cast<float>(1.0 / qm) : 0.f;
+    if constexpr (DIRECT) qvl[m] = qm;
+  }
+
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll 1
+  for (int J = sp.Ja; J < sp.Jb; ++J) {
+    const int j0 = J * BJ;
+    const int j1 = min(n, j0 + BJ);
+    __syncthreads();
+    for (int k = lane; k < 3 * BJ; k += kWave) gjl[k] = 0.0;
+#pragma unroll 1
+    for (int u0 = j0; u0 < j1; u0 += kPaSub) {
+      const int ns = min(kPaSub, j1 - u0);
+      __syncthreads();
+      const int ty = lane < ns ? clamp_type(a.tsort[d.atom_off + u0 + lane], a.T) : 0;  // row 0 past the run
+      if (lane < ns) sj[lane] = a.xyz[d.atom_off + u0 + lane];
+      for (int e = lane; e < E4; e += kWave) {
+        const int r = e / Q4;
+        const int c = e - r * Q4;
+        const int tr = __shfl(ty, r, kWave);
+        reinterpret_cast<float4*>(&fj[0][0])[e] =
+            *reinterpret_cast<const float4*>(a.tabp + static_cast<int64_t>(tr) * a.ldt + m0 + 4 * c);
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int jl = u0; jl < u0 + ns; ++jl) {
+        asm volatile("" ::: "memory");
+        const double4 pj = sj[jl - u0];
+        const float* f = fj[jl - u0];
+        const bool use = vi && jl > i;
+        double cx, cy, cz;
+        if constexpr (DIRECT) {
+          const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double ir = rsqrt_f64(fmax(r2, 1e-60));
+          const double rp = fmax(r2, 1e-60) * ir * kOneOverPi;
+          float cc = 0.f, ss = 0.f;
+          // (fully unrolled: a runtime index would put wi and wiq in scratch)
+#pragma unroll
+          for (int m = 0; m < QA; ++m) {
+            const SinCosF e = sincos_qr(qvl[m], rp);
+            const float u = wi[m] * f[m];
+            cc = fmaf(u, e.c, cc);
+            ss = fmaf(u * iql[m], e.s, ss);
+          }
+          const double G = adj_force_direct(use && r2 > 0.0, ir, cc, ss);
+          cx = G * dx;
+          cy = G * dy;
+          cz = G * dz;
+        } else {
+          const AdjSeed A = adj_seed(pi, pj, use, dq, qs);
+          float z = A.z, dd = A.d;
+          float a1e = 0.f, a1o = 0.f, a2e = 0.f, a2o = 0.f, a3e = 0.f, a3o = 0.f;
+#pragma unroll
+          for (int m = 0; m < QA; m += 2) {
+            const float ue = wi[m] * f[m], ve = ue * iql[m];
+            a1e = fmaf(ue, dd, a1e);
+            a2e = fmaf(ue, z, a2e);
+            a3e = fmaf(ve, z, a3e);
+            z += dd;
+            dd = fmaf(A.nlam, z, dd);
+            const float uo = wi[m + 1] * f[m + 1], vo = uo * iql[m + 1];
+            a1o = fmaf(uo, dd, a1o);
+            a2o = fmaf(uo, z, a2o);
+            a3o = fmaf(vo, z, a3o);
+            z += dd;
+            dd = fmaf(A.nlam, z, dd);
+          }
+          const double G = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, wi[0] * f[0]);
+          cx = G * A.dx;
+          cy = G * A.dy;
+          cz = G * A.dz;
+        }
+        gx += cx;
+        gy += cy;
+        gz += cz;
+        const float sx = wave_total(static_cast<float>(cx));
+        const float sy = wave_total(static_cast<float>(cy));
+        const float sz = wave_total(static_cast<float>(cz));
+        if (lane == 0) {
+          double* gj = gjl + 3 * (jl - j0);
+          gj[0] -= sx;
+          gj[1] -= sy;
+          gj[2] -= sz;
+        }
+      }
+    }
+    __syncthreads();
+    double* outj = a.gJ + (pidx * a.geo.g * BJ + static_cast<int64_t>(J - sp.Ja) * BJ) * 3;
+    for (int k = lane; k < 3 * (j1 - j0); k += kWave) outj[k] = gjl[k];
+  }
+  double* outi = a.gI + pidx * kWave * 3;
+  outi[3 * lane + 0] = gx;
+  outi[3 * lane + 1] = gy;
+  outi[3 * lane + 2] = gz;
+}
+
 // One thread per (sorted) atom: the i-side rows of its own row of strips and
 // the j-side rows of every strip that holds its J block, in a fixed order;
 // the sum is written to the caller's row perm[a].
@@ -376,6 +522,24 @@ hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st) {
       else
         hipLaunchKernelGGL((k_adjoint<256, false>), grid, dim3(kWave), 0, st, a);
       break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_pa(const AdjArgs& a, int32_t nchunks, int32_t qa_template, hipStream_t st) {
+  if (a.n_strips <= 0) return hipSuccess;
+  if (a.geo.bj != kAdjPaBJ || a.geo.ib != kWave || a.qa > qa_template) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<uint32_t>(a.n_strips), nchunks);
+  if (a.qdev) {
+    if (qa_template != 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adjoint_pa<64, true>), grid, dim3(kWave), 0, st, a);
+    return hipGetLastError();
+  }
+  switch (qa_template) {
+    case 32: hipLaunchKernelGGL((k_adjoint_pa<32, false>), grid, dim3(kWave), 0, st, a); break;
+    case 64: hipLaunchKernelGGL((k_adjoint_pa<64, false>), grid, dim3(kWave), 0, st, a); break;
+    case 100: hipLaunchKernelGGL((k_adjoint_pa<100, false>), grid, dim3(kWave), 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -132,6 +132,7 @@ struct Schedule {
   Geometry geo_adj{};
   int64_t n_strips_adj = 0;
   int32_t qa = 0, nchunks_adj = 0;
+  int32_t qa_template = 0;  // per-atom adjoint kernel template (>= qa)
   int32_t S = 0;
   int64_t n_total = 0;
   int64_t n_pack = 0, n_strips = 0, n_slices = 0;
@@ -320,6 +321,26 @@ void add_adjoint(Schedule* sc, int64_t n, int32_t Nq) {
   qa = (qa + 7) / 8 * 8;
   sc->qa = std::min(qa, static_cast<int32_t>(sas::kAdjQ));
   sc->nchunks_adj = (Nq + sc->qa - 1) / sc->qa;
+}
+
+// The per-atom adjoint: I blocks of 64 atoms, J blocks of kAdjPaBJ; balanced
+// chunks of at most 100 q values (64 in the direct variant), a multiple of 4
+// each, run by the smallest kernel template that holds them; the padded
+// table covers every chunk's template width.
+void add_adjoint_pa(Schedule* sc, int64_t n, int32_t Nq) {
+  sc->grad = true;
+  sc->geo_adj.bj = sas::kAdjPaBJ;
+  sc->geo_adj.ib = sas::kWave;
+  sc->geo_adj.c = sas::kAdjPaBJ / sas::kWave;
+  sc->geo_adj.g = 1;
+  sc->n_strips_adj = sas::strips_of(n, sc->geo_adj);
+  const int32_t cap = sc->direct ? 64 : 100;
+  const int32_t nch = (Nq + cap - 1) / cap;
+  const int32_t qa = std::min(cap, ((Nq + nch - 1) / nch + 3) / 4 * 4);
+  sc->qa = qa;
+  sc->qa_template = sc->direct ? 64 : (qa <= 32 ? 32 : (qa <= 64 ? 64 : 100));
+  sc->nchunks_adj = (Nq + qa - 1) / qa;
+  sc->ldt = std::max(sc->ldt, ((sc->nchunks_adj - 1) * qa + sc->qa_template + 3) / 4 * 4);
 }
 
 Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
@@ -789,8 +810,7 @@ sas_status sas_read_timing(sas_ctx* ctx, double* forward_ms, int64_t* forward_la
 }
 
 size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int grad) {
-  const int32_t max_t = grad == 1 ? SAS_MAX_TYPES : SAS_MAX_TABLE_TYPES;
-  if (check_sizes(n, t, nq, max_t) != SAS_OK) return 0;
+  if (check_sizes(n, t, nq, SAS_MAX_TABLE_TYPES) != SAS_OK) return 0;
   const std::vector<int64_t> sizes{n};
   if (grad == 2) {
     size_t need = 0;
@@ -801,11 +821,16 @@ size_t sas_debye_workspace_size(const sas_ctx* ctx, int64_t n, int32_t t, int32_
     return need;
   }
   if (grad) {
-    // the type form; the recurrence or, for a non-uniform grid, the direct variants
+    // the type or the per-atom form; the recurrence or, for a non-uniform
+    // grid, the direct variants
+    const bool pa = use_per_atom(ctx, t, n);
     size_t need = 0;
     for (bool direct : {false, true}) {
-      Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, direct);
-      add_adjoint(&sc, n, nq);
+      Schedule sc = make_schedule(ctx, sizes, t, nq, 0, 0, direct, pa);
+      if (pa)
+        add_adjoint_pa(&sc, n, nq);
+      else
+        add_adjoint(&sc, n, nq);
       need = std::max(need, make_layout(sc, t, nq).total);
     }
     return need;
@@ -1156,7 +1181,7 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
                           int32_t t, const double* q, int32_t nq, const double* dL_dI, double* grad_out,
                           double* I_out, void* workspace, size_t ws_bytes, void* stream) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  sas_status st = check_sizes(n, t, nq, SAS_MAX_TYPES);
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TABLE_TYPES);
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types || !grad_out)) return fail(SAS_ERR_INVALID_ARG, "coords/types/grad_out is NULL");
   if (!table || !dL_dI) return fail(SAS_ERR_INVALID_ARG, "table/dL_dI is NULL");
@@ -1164,9 +1189,14 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   const double q0 = grid.q0, dq = grid.dq;
-  // a non-uniform grid takes the direct variants of the forward and the adjoint
-  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform);
-  add_adjoint(&sc, n, nq);
+  // a non-uniform grid takes the direct variants of the forward and the
+  // adjoint; many table rows (or a forced per-atom form) the per-atom ones
+  const bool pa = use_per_atom(ctx, t, n);
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform, pa);
+  if (pa)
+    add_adjoint_pa(&sc, n, nq);
+  else
+    add_adjoint(&sc, n, nq);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -1185,10 +1215,15 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
     if (st != SAS_OK) return st;
   } else {
     SAS_HIP(sas::launch_pad_table(table, t, nq, sc.ldt, reinterpret_cast<float*>(w + L.tabp), hs));
-    SAS_HIP(sas::launch_pack(coords, types, view_of(sc, workspace, L), sc.S, sc.n_pack, t,
-                             reinterpret_cast<int32_t*>(w + L.bcount), reinterpret_cast<int32_t*>(w + L.toff),
-                             reinterpret_cast<double4*>(w + L.xyz), reinterpret_cast<int32_t*>(w + L.tsort),
-                             reinterpret_cast<int32_t*>(w + L.perm), hs));
+    if (pa)
+      SAS_HIP(sas::launch_pack_plain(coords, types, n, t, reinterpret_cast<double4*>(w + L.xyz),
+                                     reinterpret_cast<int32_t*>(w + L.tsort), reinterpret_cast<int32_t*>(w + L.perm),
+                                     hs));
+    else
+      SAS_HIP(sas::launch_pack(coords, types, view_of(sc, workspace, L), sc.S, sc.n_pack, t,
+                               reinterpret_cast<int32_t*>(w + L.bcount), reinterpret_cast<int32_t*>(w + L.toff),
+                               reinterpret_cast<double4*>(w + L.xyz), reinterpret_cast<int32_t*>(w + L.tsort),
+                               reinterpret_cast<int32_t*>(w + L.perm), hs));
   }
   if (n == 0) return SAS_OK;
   sas::AdjArgs a;
@@ -1197,7 +1232,7 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   a.geo = sc.geo_adj;
   a.xyz = reinterpret_cast<const double4*>(w + L.xyz);
   a.tsort = reinterpret_cast<const int32_t*>(w + L.tsort);
-  a.toff = reinterpret_cast<const int32_t*>(w + L.toff);
+  a.toff = pa ? nullptr : reinterpret_cast<const int32_t*>(w + L.toff);
   a.tabp = reinterpret_cast<const float*>(w + L.tabp);
   a.ldt = sc.ldt;
   a.T = t;
@@ -1212,7 +1247,10 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   a.qdev = sc.direct ? reinterpret_cast<const double*>(w + L.qdev) : nullptr;
   {
     LaunchTimer timer(ctx, hs, true);
-    SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));
+    if (pa)
+      SAS_HIP(sas::launch_adjoint_pa(a, sc.nchunks_adj, sc.qa_template, hs));
+    else
+      SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));
   }
   SAS_HIP(sas::launch_grad_reduce(a, n, sc.nchunks_adj, reinterpret_cast<const int32_t*>(w + L.perm), grad_out, hs));
   return SAS_OK;

@@ -61,6 +61,7 @@ struct ForwardArgs {
 };
 
 constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
+constexpr int kAdjPaBJ = 128; // J-block atoms of the per-atom adjoint
 
 struct AdjArgs {
   DescView sd;          // one structure
@@ -174,6 +175,10 @@ hipError_t launch_rows_by_type(const int32_t* keys, const int32_t* atoms, int32_
 bool pa_qc_supported(int32_t qc);
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st);
+// Per-atom form factors (no type sort): I blocks of 64 atoms (one per lane),
+// J blocks of kAdjPaBJ, a.qa <= qa_template q values per chunk (templates 32,
+// 64 and 100; the direct variant 64).
+hipError_t launch_adjoint_pa(const AdjArgs& a, int32_t nchunks, int32_t qa_template, hipStream_t st);
 hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, const int32_t* perm, double* grad_out,
                               hipStream_t st);
 bool adjoint_bj_supported(int32_t bj);

@@ -137,8 +137,9 @@ def test_per_atom_variants_and_determinism(sd, bj):
 
 
 def test_more_rows_than_the_type_sort_takes(sd):
-    """6,000 atoms with 6,000 table rows (above 4,096): profiles take the
-    per-atom form; the gradient refuses the table (status 3)."""
+    """6,000 atoms with 6,000 table rows (above 4,096): profiles and the
+    coordinate gradient take the per-atom form; sampled atoms of the gradient
+    against the oracle."""
     import torch
 
     say("T = N = 6000 > 4096")
@@ -147,9 +148,11 @@ def test_more_rows_than_the_type_sort_takes(sd):
     check(sd, m, ctx=ctx, pick=np.array([0, 1, 13, 27, 39]))
     assert ctx.form() == "recurrence+per_atom"
     c, t, tab = to_dev(m)
-    with pytest.raises(sd.SasError) as e:
-        sd.debye_grad(c, t, tab, m.q, torch.ones(40, dtype=torch.float64, device="cuda"))
-    assert e.value.status == 3
+    w = np.random.default_rng(5).normal(size=40)
+    g = sd.debye_grad(c, t, tab, m.q, torch.from_numpy(w).cuda()).cpu().numpy()
+    sub = np.arange(0, 6000, 211)
+    ref = oracle.grad(m.coords, m.types, m.table, m.q, w, atoms=sub)
+    assert np.linalg.norm(g[sub] - ref) / np.linalg.norm(ref) <= 1e-5
 
 
 def test_per_atom_batched_and_plan(sd):
