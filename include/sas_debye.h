@@ -232,7 +232,8 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
  * SAS_HYBRID_ORIENT_ALL averages every q (at most 2^17 directions per chunk
  * of 16 q, SAS_ERR_UNSUPPORTED beyond); SAS_HYBRID_DIRECT_ALL is the direct
  * sum.  tol in [1e-15, 1e-2].  *n_orient (host, may be NULL) receives the
- * number of leading q values that were averaged.  t <= SAS_MAX_TYPES.  This
+ * number of leading q values that were averaged.  t <= SAS_MAX_TABLE_TYPES
+ * (the amplitude sums take each atom's own row; no type sort).  This
  * call synchronises `stream` once (it reads the molecule's radius back to
  * choose L).  If the workspace is smaller than the query returns, fewer q
  * values are averaged (AUTO) or the call fails (ORIENT_ALL).

@@ -1390,13 +1390,12 @@ OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, d
 // Workspace of the orientation part: upload block (chunks, rule, q values),
 // geometry, padded table and partial amplitudes.
 struct OrientLayout {
-  size_t xyz = 0, tsort = 0, perm = 0, bcount = 0, toff = 0, geom = 0;
+  size_t xyz = 0, tsort = 0, perm = 0, geom = 0;
   size_t upload = 0, upload_bytes = 0, chunks = 0, gl = 0, qv = 0;
   size_t tabo = 0, apart = 0, tabd = 0, direct = 0, total = 0;
 };
 
-OrientLayout orient_layout(int64_t n, int32_t T, int64_t n_pack, const OrientPlan& p, int32_t nq_d,
-                           size_t direct_bytes) {
+OrientLayout orient_layout(int64_t n, int32_t T, const OrientPlan& p, int32_t nq_d, size_t direct_bytes) {
   OrientLayout L;
   size_t at = 0;
   auto take = [&](size_t bytes) {
@@ -1407,8 +1406,6 @@ OrientLayout orient_layout(int64_t n, int32_t T, int64_t n_pack, const OrientPla
   L.xyz = take(sizeof(double4) * n);
   L.tsort = take(sizeof(int32_t) * n);
   L.perm = take(sizeof(int32_t) * n);
-  L.bcount = take(sizeof(int32_t) * n_pack * T);
-  L.toff = take(sizeof(int32_t) * (T + 1));
   L.geom = take(sizeof(double) * 4);
   const size_t cb = align_up(sizeof(sas::OrientChunk) * p.chunks.size());
   const size_t gb = align_up(sizeof(double) * p.gl.size());
@@ -1443,7 +1440,6 @@ size_t orient_bound_bytes(int64_t n, int32_t t, int32_t nq, int64_t cap) {
   const int64_t L = static_cast<int64_t>(std::sqrt(static_cast<double>(cap) / 2.0)) + 2;
   size_t b = 0;
   b += align_up(sizeof(double4) * n) + 2 * align_up(sizeof(int32_t) * n);
-  b += align_up(sizeof(int32_t) * cdiv(n, int64_t(sas::kPackBlock)) * t) + align_up(sizeof(int32_t) * (t + 1));
   b += 256 + align_up(sizeof(sas::OrientChunk) * nch) + align_up(sizeof(double) * 2 * nch * (L + 1)) +
        align_up(sizeof(double) * nq) + 256;
   b += align_up(sizeof(float) * t * nch * sas::kOrientQ);
@@ -1471,7 +1467,7 @@ int32_t sas_orient_degree(double q, double r_max, double tol) {
 }
 
 size_t sas_debye_workspace_size_hybrid(const sas_ctx* ctx, int64_t n, int32_t t, int32_t nq, int32_t mode) {
-  if (check_sizes(n, t, nq, SAS_MAX_TYPES) != SAS_OK) return 0;
+  if (check_sizes(n, t, nq, SAS_MAX_TABLE_TYPES) != SAS_OK) return 0;
   if (mode < SAS_HYBRID_AUTO || mode > SAS_HYBRID_DIRECT_ALL) return 0;
   const int64_t cap = std::max(orient_cap(n, mode, true, true), orient_cap(n, mode, false, true));
   // (the pack, geometry and table-copy regions precede the direct part in every mode)
@@ -1486,7 +1482,7 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
                                     int32_t mode, double* I_out, void* workspace, size_t ws_bytes, void* stream,
                                     int32_t* n_orient) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  sas_status st = check_sizes(n, t, nq, SAS_MAX_TYPES);
+  sas_status st = check_sizes(n, t, nq, SAS_MAX_TABLE_TYPES);
   if (st != SAS_OK) return st;
   if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
   if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
@@ -1504,20 +1500,18 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   if (st != SAS_OK) return st;
   char* w = static_cast<char*>(workspace);
 
-  // 1. pack (type sort) and geometry; the radius decides the quadrature, so
-  //    it is read back here (the one synchronisation of this call)
-  const Schedule sp = make_schedule(ctx, std::vector<int64_t>{n}, t, nq);
+  // 1. FP64 copy of the coordinates (caller order: the amplitude sums need no
+  //    type sort, so any number of table rows works) and geometry; the radius
+  //    decides the quadrature, so it is read back here (the one
+  //    synchronisation of this call)
   OrientPlan none;
-  OrientLayout L0 = orient_layout(n, t, sp.n_pack, none, 0, 0);
+  OrientLayout L0 = orient_layout(n, t, none, 0, 0);
   if (ws_bytes < L0.total) return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", ws_bytes, L0.total);
   double geom[4] = {0.0, 0.0, 0.0, 0.0};
   if (mode != SAS_HYBRID_DIRECT_ALL && n > 0) {
-    Layout Lp;
-    Lp.desc = 0;
-    SAS_HIP(sas::launch_pack(coords, types, view_of(sp, workspace, Lp), 1, sp.n_pack, t,
-                             reinterpret_cast<int32_t*>(w + L0.bcount), reinterpret_cast<int32_t*>(w + L0.toff),
-                             reinterpret_cast<double4*>(w + L0.xyz), reinterpret_cast<int32_t*>(w + L0.tsort),
-                             reinterpret_cast<int32_t*>(w + L0.perm), hs));
+    SAS_HIP(sas::launch_pack_plain(coords, types, n, t, reinterpret_cast<double4*>(w + L0.xyz),
+                                   reinterpret_cast<int32_t*>(w + L0.tsort), reinterpret_cast<int32_t*>(w + L0.perm),
+                                   hs));
     SAS_HIP(sas::launch_geometry(reinterpret_cast<const double4*>(w + L0.xyz), n, reinterpret_cast<double*>(w + L0.geom),
                                  hs));
     SAS_HIP(hipMemcpyAsync(geom, w + L0.geom, sizeof(geom), hipMemcpyDeviceToHost, hs));
@@ -1560,7 +1554,7 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
     bool over = false;
     for (const auto& ch : plan.chunks) over = over || static_cast<int64_t>(ch.nth) * ch.nph > cap;
     const int32_t nq_d = nq - nq_o;
-    L = orient_layout(n, t, sp.n_pack, plan, nq_d, direct_part_bytes(ctx, n, t, nq_d));
+    L = orient_layout(n, t, plan, nq_d, direct_part_bytes(ctx, n, t, nq_d));
     if (!over && L.total <= ws_bytes) break;
     if (mode == SAS_HYBRID_ORIENT_ALL) {
       if (over) return fail(SAS_ERR_UNSUPPORTED, "orientation average needs more than %lld directions", (long long)cap);

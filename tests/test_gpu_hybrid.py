@@ -101,6 +101,23 @@ def test_coarse_uniform_grid_uses_per_q_sines(sd):
     assert rel_err(I.cpu().numpy(), ref).max() <= TOL
 
 
+def test_per_atom_rows_above_the_type_sort(sd):
+    """6,000 atoms with one table row each (above 4,096 rows): every q
+    averaged, and the automatic split, against the oracle at sampled q."""
+    say("orientation average with T = N = 6000 rows")
+    m = W.with_per_atom_factors(_globule(6000, W.q_grid(0.0, 0.3, 48), 13062258 + 62), 13062258 + 63)
+    c, t, tab = to_dev(m)
+    pick = np.array([0, 1, 15, 16, 30, 47])
+    ref = oracle.profile(m.coords, m.types, m.table[:, pick], m.q[pick])
+    for mode in ("orient", "auto"):
+        I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10, mode=mode)
+        if mode == "orient":
+            assert n_o == len(m.q)
+        err = rel_err(I.cpu().numpy()[pick], ref)
+        print(f"{mode}: {n_o} q averaged, sampled errors", " ".join(f"{e:.2e}" for e in err))
+        assert err.max() <= TOL
+
+
 def test_direct_mode_equals_plain_profile(sd):
     say("hybrid in direct mode is the plain profile, bitwise")
     m = W.random_molecule(1830, 1200, 77, q0=0.0, q1=1.0, extent=30.0)
