@@ -95,10 +95,21 @@ def stored_valu(kernel_name: str, work: float, kern_ms: float):
     except (KeyError, ValueError):
         return None
     tflops = flops / (kern_ms / 1e3) / 1e12
-    return {"executed_fp32_flops_per_pair_q": flops / work, "executed_fp32_tflops": tflops,
-            "frac_of_fp32_peak": tflops / PEAK_FP32_TFLOPS, "valu_insts_per_pair_q": insts * 64.0 / work,
-            "cycles_per_valu_inst_per_simd": (kern_ms / 1e3) * 2.4e9 / (insts / 1024.0),
-            "source": os.path.relpath(VALU_FILE, ROOT)}
+    out = {"executed_fp32_flops_per_pair_q": flops / work, "executed_fp32_tflops": tflops,
+           "frac_of_fp32_peak": tflops / PEAK_FP32_TFLOPS, "valu_insts_per_pair_q": insts * 64.0 / work,
+           "cycles_per_valu_inst_per_simd": (kern_ms / 1e3) * 2.4e9 / (insts / 1024.0),
+           "source": os.path.relpath(VALU_FILE, ROOT)}
+    # GRBM_GUI_ACTIVE counts busy cycles of each of the 8 XCDs: over the
+    # kernel's time it gives the clock the chip actually ran at, and the peak
+    # scaled to that clock
+    try:
+        ghz = float(kv["GRBM_GUI_ACTIVE"]) / 8.0 / (kern_ms / 1e3) / 1e9
+    except (KeyError, ValueError):
+        ghz = None
+    if ghz:
+        out["effective_clock_ghz"] = ghz
+        out["peak_fp32_tflops_at_clock"] = PEAK_FP32_TFLOPS * ghz / 2.4
+    return out
 
 
 def log(msg):
@@ -222,6 +233,9 @@ def main(argv=None):
                      "issue_frac": (work / (kern_ms / 1e3)) / ISSUE_CEILING_PAIR_Q,
                      "valu_counters": stored_valu(kname, work, kern_ms)},
     }
+    vc = result["roofline"]["valu_counters"]
+    if vc and vc.get("peak_fp32_tflops_at_clock"):
+        result["roofline"]["frac_clock_adjusted"] = achieved / vc["peak_fp32_tflops_at_clock"]
 
     # accuracy of the timed output against the stored FP64 oracle profile
     gold = os.path.join(ROOT, "tests", "golden", "dna_rod_50k.txt")
