@@ -143,6 +143,12 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
         const PairSeed B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
         asm volatile("" ::: "memory");
         float za = A.z, da = A.d, zb = B.z, db = B.d;
+        // (the negated lambdas are laundered through an empty asm: known to be
+        // negations, they would be folded into a source modifier, which needs the
+        // 64-bit VOP3 encoding of the FMA; a plain register operand keeps the 32-bit
+        // v_fmac form, which issues faster on gfx950)
+        float nla = A.nlam, nlb = B.nlam;
+        asm volatile("" : "+v"(nla), "+v"(nlb));
 #pragma unroll
         for (int m = 0; m < QC; ++m) {
           if (m & 1) {
@@ -154,8 +160,8 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
           }
           za += da;
           zb += db;
-          da = fmaf(A.nlam, za, da);
-          db = fmaf(B.nlam, zb, db);
+          da = fmaf(nla, za, da);
+          db = fmaf(nlb, zb, db);
         }
       }
       }

@@ -194,6 +194,8 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           const float* fa = fj[jl - u0];
           const float* fb = fj[jb - u0];
           float za = A.z, da = A.d, zb = B.z, db = B.d;
+          float nla = A.nlam, nlb = B.nlam;  // laundered: see the type-segment form
+          asm volatile("" : "+v"(nla), "+v"(nlb));
 #pragma unroll
           for (int m = 0; m < QC; ++m) {
             if (m & 1) {
@@ -205,8 +207,8 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
             }
             za += da;
             zb += db;
-            da = fmaf(A.nlam, za, da);
-            db = fmaf(B.nlam, zb, db);
+            da = fmaf(nla, za, da);
+            db = fmaf(nlb, zb, db);
           }
         }
       }
