@@ -1265,7 +1265,7 @@ namespace {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 constexpr int64_t kOrientCapAll = int64_t(1) << 17;  // directions per chunk when every q is averaged
-constexpr int64_t kOrientBlocksTarget = 4096;          // work-groups the amplitude kernel aims for
+constexpr int64_t kOrientBlocksTarget = 16384;         // most work-groups the amplitude kernel takes
 // Time per unit, in pair*q steps of the type-form recurrence (measured on
 // MI355X): the per-pair set-up of the recurrence (about 66 steps), a step of
 // the direct form (4.3) and its set-up (5), and an atom*direction*q of the
@@ -1348,7 +1348,7 @@ struct OrientPlan {
   int32_t ldo = 0;          // row stride of the orientation table
 };
 
-OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, double tol) {
+OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, double tol, int64_t slots) {
   OrientPlan p;
   p.nq_o = nq_o;
   if (nq_o <= 0) return p;
@@ -1374,8 +1374,24 @@ OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, d
     p.chunks.push_back(ch);
   }
   p.total_blocks = blk;
-  const int64_t max_parts = std::max<int64_t>(1, cdiv(n, int64_t(256)));
-  p.parts = static_cast<int32_t>(std::min(max_parts, std::max<int64_t>(1, cdiv(kOrientBlocksTarget, blk))));
+  // Every work-group does the same work (atoms_per_part atoms for 64
+  // directions and 16 q), so the kernel takes about ceil(blk parts / slots)
+  // rounds of 1/parts of the atoms each: choose the part count that makes
+  // that smallest (the last round of a poor choice runs mostly empty), the
+  // fewest parts among equals; at most kOrientBlocksTarget work-groups
+  // (the workspace bound) and 256 atoms per part.
+  const int64_t max_parts = std::max<int64_t>(
+      1, std::min(cdiv(n, int64_t(256)), cdiv(kOrientBlocksTarget, std::max<int64_t>(blk, 1))));
+  int64_t best = 1;
+  double best_t = 1e300;
+  for (int64_t parts = 1; parts <= max_parts; ++parts) {
+    const double t = static_cast<double>(cdiv(blk * parts, std::max<int64_t>(slots, 1))) / static_cast<double>(parts);
+    if (t < best_t * (1.0 - 1e-9)) {
+      best_t = t;
+      best = parts;
+    }
+  }
+  p.parts = static_cast<int32_t>(best);
   p.atoms_per_part = static_cast<int32_t>(cdiv(cdiv(std::max<int64_t>(n, 1), int64_t(p.parts)),
                                                         int64_t(sas::kPaSub)) * sas::kPaSub);
   int64_t off = 0;
@@ -1550,7 +1566,8 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   OrientPlan plan;
   OrientLayout L;
   for (;;) {
-    plan = plan_orient(n, q, nq_o, r_max, tol);
+    plan = plan_orient(n, q, nq_o, r_max, tol,
+                       static_cast<int64_t>(ctx->cu_count) * sas::orient_wgs_per_cu(orient_rot(q, nq_o, r_max, nullptr)));
     bool over = false;
     for (const auto& ch : plan.chunks) over = over || static_cast<int64_t>(ch.nth) * ch.nph > cap;
     const int32_t nq_d = nq - nq_o;

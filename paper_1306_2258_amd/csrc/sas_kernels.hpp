@@ -146,6 +146,8 @@ constexpr double kRotMaxStep = 0.5;
 
 hipError_t launch_geometry(const double4* xyz, int64_t n, double* out, hipStream_t st);
 hipError_t launch_orient(const OrientArgs& a, int64_t total_blocks, int32_t nq_o, double* I_out, hipStream_t st);
+// Work-groups of the amplitude kernel that fit on one CU at once.
+int orient_wgs_per_cu(bool rot);
 hipError_t launch_copy_cols(const float* src, int32_t T, int32_t ld_src, int32_t col0, int32_t ncols, int32_t ldt,
                             float* dst, hipStream_t st);
 

@@ -272,6 +272,13 @@ hipError_t launch_orient(const OrientArgs& a, int64_t total_blocks, int32_t nq_o
   return hipGetLastError();
 }
 
+int orient_wgs_per_cu(bool rot) {
+  int k = 0;
+  const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_orient_amp<true>, kWave, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, k_orient_amp<false>, kWave, 0);
+  return e == hipSuccess && k > 0 ? k : 4 * 2;
+}
+
 hipError_t launch_copy_cols(const float* src, int32_t T, int32_t ld_src, int32_t col0, int32_t ncols, int32_t ldt,
                             float* dst, hipStream_t st) {
   const int64_t total = static_cast<int64_t>(T) * ldt;
