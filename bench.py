@@ -43,18 +43,30 @@ ISSUE_CEILING_PAIR_Q = 1024 * 2.4e9 * 64 / (INSTR_PER_PAIR_Q * MIX_CYCLES_PER_WA
 BASE_SEED_PER_ATOM = 13062258 + 50
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "k_forward_dna_rod_50k_valu.txt")
+# What the headline pair kernel's code depends on: its template and device
+# helpers, and the argument structs and wave size from the internal header
+# (the rest of that header and of the .hip files declares or defines other
+# kernels, which do not change this one).
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1306_2258_amd", "csrc", f)
-                  for f in ("sas_kernels.hip", "sas_forward_kernel.hpp", "sas_forward.hpp", "sas_device.hpp",
-                            "sas_schedule.hpp", "sas_kernels.hpp")]
+                  for f in ("sas_forward_kernel.hpp", "sas_forward.hpp", "sas_device.hpp", "sas_schedule.hpp")]
+KERNEL_HEADER = os.path.join(ROOT, "paper_1306_2258_amd", "csrc", "sas_kernels.hpp")
+KERNEL_HEADER_PARTS = ("kWave", "StructDesc", "DescView", "Geometry", "ForwardArgs")
 
 
 def kernel_source_hash() -> str:
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
+    with open(KERNEL_HEADER) as fh:
+        text = fh.read()
+    for name in KERNEL_HEADER_PARTS:
+        m = (re.search(r"constexpr int " + name + r" = [^;]*;", text) or
+             re.search(r"struct " + name + r" \{.*?\n\};", text, re.S))
+        h.update((m.group(0) if m else name + " missing").encode())
     return h.hexdigest()[:16]
 
 
