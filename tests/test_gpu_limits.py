@@ -1,0 +1,115 @@
+"""The library's stated limits at their edges, on the GPU: the largest q
+count (SAS_MAX_NQ = 65,536) on a uniform and on a log-spaced grid, and the
+largest table (SAS_MAX_TABLE_TYPES = 2^24 rows) with atoms on its last rows,
+for the profile and both gradients, against the FP64 oracle; one past each
+limit is refused with SAS_ERR_UNSUPPORTED before any device work.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MAX_NQ = 65536
+MAX_T = 1 << 24
+UNSUPPORTED = 3
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1306_2258_amd as mod
+
+    return mod
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(m):
+    import torch
+
+    return (torch.from_numpy(m.coords).cuda(), torch.from_numpy(m.types).cuda(), torch.from_numpy(m.table).cuda())
+
+
+def rel_err(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+@pytest.mark.parametrize("grid", ["uniform", "log"])
+def test_max_q_count(sd, grid):
+    say(f"Nq = {MAX_NQ} ({grid} grid), N = 40")
+    q = W.q_grid(0.0, 2.0, MAX_NQ) if grid == "uniform" else W.log_grid(1e-3, 2.0, MAX_NQ)
+    m = W.random_molecule(2300, 40, 0, t=3, q=q, extent=12.0)
+    c, t, tab = to_dev(m)
+    got = sd.debye_profile(c, t, tab, m.q).cpu().numpy()
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    err = rel_err(got, ref)
+    print(f"max rel err {err.max():.3e}")
+    assert err.max() <= 1e-6
+
+
+def test_q_count_past_limit(sd):
+    say(f"Nq = {MAX_NQ + 1} is refused")
+    m = W.random_molecule(2301, 10, MAX_NQ + 1, t=2, q0=0.0, q1=1.0, extent=8.0)
+    c, t, tab = to_dev(m)
+    with pytest.raises(sd.SasError) as e:
+        sd.debye_profile(c, t, tab, m.q)
+    assert e.value.status == UNSUPPORTED
+
+
+def _max_table(seed, n, nq, rows):
+    """n atoms on table rows near the top of a `rows`-row table (and row 0):
+    every row Z exp(-B q^2) with Z, B from the row index, filled in place."""
+    m = W.random_molecule(seed, n, nq, t=1, q0=0.0, q1=0.8, extent=14.0)
+    rng = W.rng_for(seed + 1)
+    types = rng.integers(rows - 200, rows, size=n).astype(np.int32)
+    types[:3] = 0
+    z = 1.0 + (np.arange(rows, dtype=np.float64) % 16.0)
+    b = 0.2 + 1.3 * ((np.arange(rows, dtype=np.float64) * 0.6180339887) % 1.0)
+    table = np.empty((rows, nq), dtype=np.float32)
+    for k in range(nq):
+        table[:, k] = (z * np.exp(-b * m.q[k] ** 2)).astype(np.float32)
+    return W.Molecule("max_table", m.coords, types, table, m.q)
+
+
+def test_max_table_rows(sd):
+    import torch
+
+    say(f"T = {MAX_T} rows, N = 60, Nq = 4: profile, coordinate and table gradients")
+    m = _max_table(2310, 60, 4, MAX_T)
+    c, t, tab = to_dev(m)
+    I = sd.debye_profile(c, t, tab, m.q).cpu().numpy()
+    Iref = oracle.profile(m.coords, m.types, m.table, m.q)
+    assert rel_err(I, Iref).max() <= 1e-6
+    w = np.array([0.3, -1.0, 2.0, 0.5])
+    wd = torch.from_numpy(w).cuda()
+    g = sd.debye_grad(c, t, tab, m.q, wd).cpu().numpy()
+    gref = oracle.grad(m.coords, m.types, m.table, m.q, w)
+    assert np.linalg.norm(g - gref) / np.linalg.norm(gref) <= 1e-5
+    gt = sd.debye_grad_table(c, t, tab, m.q, wd)
+    used = np.unique(m.types)
+    got = gt[torch.from_numpy(used).long().cuda()].cpu().numpy()
+    ref = oracle.grad_table(m.coords, m.types, m.table, m.q, w)[used]
+    assert np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)) <= 1e-5
+    assert float(gt.abs().sum()) == pytest.approx(float(np.abs(got).sum()), rel=1e-12)  # unused rows are zero
+
+
+def test_table_rows_past_limit(sd):
+    say(f"T = {MAX_T + 1} rows is refused")
+    m = _max_table(2320, 8, 1, MAX_T + 1)
+    c, t, tab = to_dev(m)
+    with pytest.raises(sd.SasError) as e:
+        sd.debye_profile(c, t, tab, m.q)
+    assert e.value.status == UNSUPPORTED
