@@ -61,10 +61,14 @@ __device__ __forceinline__ float wave_total(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Per-pair FP64 set-up shared by the two atoms of a lane.
+// Per-pair FP64 set-up shared by the two atoms of a lane.  The values the
+// pair's force is formed from at the end (1/r, 1 - cos(dp), 1/sin(dp),
+// cos(q_s r)) are kept in FP32: that force combines FP32 q sums, and each
+// pair's force enters the gradient once, so one more FP32 rounding there is
+// an unbiased 6e-8 per pair against the 1e-5 the gradient is held to.
 struct AdjSeed {
   float z, d, nlam, sg;
-  double ir, omc, isdp, c0;  // 1/r, 1 - cos(dp), 1/sin(dp), cos(q_s r)
+  float ir, omc, isdp, c0;  // 1/r, 1 - cos(dp), 1/sin(dp), cos(q_s r)
   double dx, dy, dz;
   bool valid;
 };
@@ -77,8 +81,9 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   const double r2raw = fma(p.dz, p.dz, fma(p.dy, p.dy, p.dx * p.dx));
   p.valid = use && r2raw > 0.0;
   const double r2 = fmax(r2raw, 1e-60);
-  p.ir = rsqrt_f64(r2);
-  const double r = r2 * p.ir;
+  const double ir = rsqrt_f64(r2);
+  const double r = r2 * ir;
+  p.ir = static_cast<float>(ir);
   const double delta = dq * r;
   const double k = rint(delta * kOneOverPi);
   double dp = fma(-k, kPiA, delta);
@@ -88,36 +93,34 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
   const double lam = s2 * s2;     // 4 sin^2(dp/2)
   const double sdp = s2 * hh.c;   // sin(dp)
-  p.omc = 0.5 * lam;              // 1 - cos(dp) = lambda / 2
-  // 1/sin(dp): hardware estimate and two Newton steps (0 when sin(dp) = 0)
-  double y = __builtin_amdgcn_rcp(sdp);
-  y = y * fma(-sdp, y, 2.0);
-  y = y * fma(-sdp, y, 2.0);
-  p.isdp = sdp != 0.0 ? y : 0.0;
+  const double omc = 0.5 * lam;   // 1 - cos(dp) = lambda / 2
+  p.omc = static_cast<float>(omc);
+  // 1/sin(dp) by the FP32 hardware reciprocal (0 when sin(dp) = 0)
+  p.isdp = sdp != 0.0 ? __builtin_amdgcn_rcpf(static_cast<float>(sdp)) : 0.f;
   double S0 = 0.0, C0 = 1.0;
   if (qs != 0.0) {
     const SinCos t0 = sincos_any(qs * r);
     S0 = t0.s;
     C0 = t0.c;
   }
-  p.c0 = C0;
+  p.c0 = static_cast<float>(C0);
   p.z = static_cast<float>(S0);
-  p.d = static_cast<float>(fma(C0, sdp, -S0 * p.omc));
+  p.d = static_cast<float>(fma(C0, sdp, -S0 * omc));
   p.nlam = static_cast<float>(-lam);
   p.sg = parity_sign(k);
   return p;
 }
 
-// G (x_i - x_j) of one pair from its six accumulators.
+// G of one pair (its force is G (x_i - x_j)) from its six accumulators, in FP32.
 __device__ __forceinline__ double adj_force(const AdjSeed& p, float a1e, float a1o, float a2e, float a2o, float a3e,
                                             float a3o, double dq, float u0) {
-  const double A1 = static_cast<double>(a1e) + p.sg * static_cast<double>(a1o);
-  const double A2 = static_cast<double>(a2e) + p.sg * static_cast<double>(a2o);
-  const double A3 = static_cast<double>(a3e) + p.sg * static_cast<double>(a3o);
+  const float A1 = fmaf(p.sg, a1o, a1e);
+  const float A2 = fmaf(p.sg, a2o, a2e);
+  const float A3 = fmaf(p.sg, a3o, a3e);
   // sum_m U_m cos(q_m r); with a single q (dq = 0), or dq r an exact multiple
   // of pi, the recurrence is constant and the seed's cosine is used
-  const double Cc = (dq != 0.0 && p.isdp != 0.0) ? (A1 + p.omc * A2) * p.isdp : static_cast<double>(u0) * p.c0;
-  return p.valid ? 2.0 * p.ir * p.ir * (Cc - A3 * p.ir) : 0.0;
+  const float Cc = (dq != 0.0 && p.isdp != 0.f) ? fmaf(p.omc, A2, A1) * p.isdp : u0 * p.c0;
+  return p.valid ? static_cast<double>((2.f * p.ir * p.ir) * fmaf(-A3, p.ir, Cc)) : 0.0;
 }
 
 // G of one atom of the direct variant from its sums C and S.
