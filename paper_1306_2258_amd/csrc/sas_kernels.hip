@@ -54,24 +54,33 @@ __global__ __launch_bounds__(kPackBlock) void k_pack_count(const int32_t* __rest
   for (int t = threadIdx.x; t < T; t += blockDim.x) bcount[b * T + t] = cnt[t];
 }
 
-// One work-group per structure: per type, exclusive prefix over the blocks;
-// then the type segments' absolute starts toff[s][0..T] and the absolute
-// destination base of every (block, type).
+// One work-group per structure.  Per type, an exclusive scan of its per-block
+// counts (wave w takes types w, w + 4, ...; the 64 lanes scan 64 blocks at a
+// time); then the type segments' absolute starts toff[s][0..T] in type
+// order; then every block's destination base of every type is that start
+// plus its exclusive count.
 __global__ __launch_bounds__(256) void k_pack_scan(DescView sd, int32_t T, int32_t* __restrict__ bcount,
                                                    int32_t* __restrict__ toff) {
   extern __shared__ int32_t tot[];
   const int s = blockIdx.x;
   const StructDesc d = sd.get(s);
   const int64_t nb = ceil_div(d.n, kPackBlock);
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (int t = w; t < T; t += nw) {
     int32_t run = 0;
-    for (int64_t lb = 0; lb < nb; ++lb) {
+    for (int64_t b0 = 0; b0 < nb; b0 += kWave) {
+      const int64_t lb = b0 + lane;
       int32_t* p = bcount + (d.pack_off + lb) * T + t;
-      const int32_t c = *p;
-      *p = run;
-      run += c;
+      const int32_t c = lb < nb ? *p : 0;
+      int32_t x = c;  // inclusive scan over the wave
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+      }
+      if (lb < nb) *p = run + x - c;
+      run += __shfl(x, kWave - 1, kWave);
     }
-    tot[t] = run;
+    if (lane == 0) tot[t] = run;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -86,10 +95,8 @@ __global__ __launch_bounds__(256) void k_pack_scan(DescView sd, int32_t T, int32
     o[T] = static_cast<int32_t>(run);
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < T; t += blockDim.x) {
-    const int32_t base = tot[t];
-    for (int64_t lb = 0; lb < nb; ++lb) bcount[(d.pack_off + lb) * T + t] += base;
-  }
+  int32_t* base = bcount + static_cast<int64_t>(d.pack_off) * T;
+  for (int64_t k = threadIdx.x; k < nb * T; k += blockDim.x) base[k] += tot[k % T];
 }
 
 __global__ __launch_bounds__(kPackBlock) void k_pack_scatter(const float* __restrict__ coords,
@@ -215,21 +222,35 @@ hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Reduce.  Level 1: each work-group sums kSliceTiles consecutive strip rows of
-// one structure, in order.  Level 2: one work-group per structure sums its
-// slices in order and applies Eq. 2's diagonal and the 2/q factor.
+// Reduce.  Level 1: one work-group per (slice of kSliceTiles consecutive strip
+// rows of one structure, 64 columns): wave w sums its quarter of the slice's
+// rows in order, lane l one column, and the four wave sums are added in wave
+// order.  Level 2: one work-group per (structure, 64 q values) sums the
+// structure's slices the same way (wave w takes slices w, w+4, ...) and
+// applies Eq. 2's diagonal and the 2/q factor.  Every order is fixed, so the
+// results are deterministic.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce_slices(DescView sd, const double* __restrict__ partial, int32_t Nq,
                                                        double* __restrict__ slice_sums) {
+  __shared__ double part[4][kWave];
   const int64_t sl = blockIdx.x;
   const int s = find_struct_by_slice(sd, sl);
   const StructDesc d = sd.get(s);
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int64_t first = d.strip_off + (sl - d.slice_off) * kSliceTiles;
   const int64_t last = min(first + kSliceTiles, d.strip_off + d.n_strips);
-  for (int m = threadIdx.x; m < Nq; m += blockDim.x) {
+  constexpr int kQuarter = kSliceTiles / 4;
+  const int64_t a = first + w * kQuarter, b = min(last, a + kQuarter);
+  const int groups = static_cast<int>(ceil_div(Nq, kWave));
+  for (int g = blockIdx.y; g < groups; g += gridDim.y) {  // (grid.y is capped at 65535)
+    const int m = g * kWave + lane;
     double acc = 0.0;
-    for (int64_t t = first; t < last; ++t) acc += partial[t * Nq + m];
-    slice_sums[sl * Nq + m] = acc;
+    if (m < Nq)
+      for (int64_t t = a; t < b; ++t) acc += partial[t * Nq + m];
+    __syncthreads();
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && m < Nq) slice_sums[sl * Nq + m] = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
   }
 }
 
@@ -239,44 +260,58 @@ __global__ __launch_bounds__(256) void k_reduce_final(DescView sd, const double*
                                                       const float* __restrict__ table, int32_t T, int32_t Nq,
                                                       double q0, double dq, const double* __restrict__ qdev,
                                                       double* __restrict__ I_out) {
+  __shared__ double part[4][kWave];
   const int s = blockIdx.x;
   const StructDesc d = sd.get(s);
   const int32_t* o = toff ? toff + static_cast<int64_t>(s) * (T + 1) : nullptr;
   const int64_t nb = ceil_div(d.n, kPackBlock);
-  for (int m = threadIdx.x; m < Nq; m += blockDim.x) {
-    const double qm = qdev ? qdev[m] : q0 + m * dq;
-    double val;
-    if (qm == 0.0) {
-      double f = 0.0;
-      if (asum) {
-        for (int64_t k = 0; k < nb; ++k) f += asum[((d.pack_off + k) * 2 + 0) * Nq + m];
-      } else {
-        for (int t = 0; t < T; ++t) f += static_cast<double>(o[t + 1] - o[t]) * static_cast<double>(table[static_cast<int64_t>(t) * Nq + m]);
-      }
-      val = f * f;
-    } else {
-      double pairs = 0.0;
-      for (int64_t k = 0; k < d.n_slices; ++k) pairs += slice_sums[(d.slice_off + k) * Nq + m];
-      double diag = 0.0;
-      if (asum) {
-        for (int64_t k = 0; k < nb; ++k) diag += asum[((d.pack_off + k) * 2 + 1) * Nq + m];
-      } else {
-        for (int t = 0; t < T; ++t) {
-          const double f = table[static_cast<int64_t>(t) * Nq + m];
-          diag += static_cast<double>(o[t + 1] - o[t]) * f * f;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int groups = static_cast<int>(ceil_div(Nq, kWave));
+  for (int g = blockIdx.y; g < groups; g += gridDim.y) {  // (grid.y is capped at 65535)
+    const int m = g * kWave + lane;
+    const bool vm = m < Nq;
+    const double qm = vm ? (qdev ? qdev[m] : q0 + m * dq) : 1.0;
+    // the strip pair sums: wave w takes slices w, w + 4, ... in order
+    double pairs = 0.0;
+    if (vm && qm != 0.0)
+      for (int64_t k = w; k < d.n_slices; k += 4) pairs += slice_sums[(d.slice_off + k) * Nq + m];
+    __syncthreads();
+    part[w][lane] = pairs;
+    __syncthreads();
+    if (w == 0 && vm) {
+      double val;
+      if (qm == 0.0) {
+        double f = 0.0;
+        if (asum) {
+          for (int64_t k = 0; k < nb; ++k) f += asum[((d.pack_off + k) * 2 + 0) * Nq + m];
+        } else {
+          for (int t = 0; t < T; ++t)
+            f += static_cast<double>(o[t + 1] - o[t]) * static_cast<double>(table[static_cast<int64_t>(t) * Nq + m]);
         }
+        val = f * f;
+      } else {
+        const double psum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+        double diag = 0.0;
+        if (asum) {
+          for (int64_t k = 0; k < nb; ++k) diag += asum[((d.pack_off + k) * 2 + 1) * Nq + m];
+        } else {
+          for (int t = 0; t < T; ++t) {
+            const double f = table[static_cast<int64_t>(t) * Nq + m];
+            diag += static_cast<double>(o[t + 1] - o[t]) * f * f;
+          }
+        }
+        val = diag + (2.0 / qm) * psum;
       }
-      val = diag + (2.0 / qm) * pairs;
+      I_out[static_cast<int64_t>(d.orig) * Nq + m] = val;
     }
-    I_out[static_cast<int64_t>(d.orig) * Nq + m] = val;
   }
 }
 
 hipError_t launch_reduce_slices(const DescView& sd, int64_t n_slices_total, const double* partial, int32_t row,
                                 double* slice_sums, hipStream_t st) {
   if (n_slices_total > 0) {
-    hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total)), dim3(256), 0, st, sd, partial,
-                       row, slice_sums);
+    const dim3 grid(static_cast<uint32_t>(n_slices_total), static_cast<uint32_t>(std::min<int64_t>(ceil_div(row, kWave), 65535)));
+    hipLaunchKernelGGL(k_reduce_slices, grid, dim3(256), 0, st, sd, partial, row, slice_sums);
   }
   return hipGetLastError();
 }
@@ -284,13 +319,14 @@ hipError_t launch_reduce_slices(const DescView& sd, int64_t n_slices_total, cons
 hipError_t launch_reduce(const DescView& sd, int32_t S, int64_t n_slices_total, const double* partial,
                          double* slice_sums, const int32_t* toff, const double* asum, const float* table, int32_t T,
                          int32_t Nq, double q0, double dq, const double* qdev, double* I_out, hipStream_t st) {
+  const uint32_t qgroups = static_cast<uint32_t>(std::min<int64_t>(ceil_div(Nq, kWave), 65535));
   if (n_slices_total > 0) {
-    hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total)), dim3(256), 0, st, sd, partial,
-                       Nq, slice_sums);
+    hipLaunchKernelGGL(k_reduce_slices, dim3(static_cast<uint32_t>(n_slices_total), qgroups), dim3(256), 0, st, sd,
+                       partial, Nq, slice_sums);
   }
   if (S > 0) {
-    hipLaunchKernelGGL(k_reduce_final, dim3(S), dim3(256), 0, st, sd, slice_sums, toff, asum, table, T, Nq, q0, dq,
-                       qdev, I_out);
+    hipLaunchKernelGGL(k_reduce_final, dim3(S, qgroups), dim3(256), 0, st, sd, slice_sums, toff, asum, table, T, Nq,
+                       q0, dq, qdev, I_out);
   }
   return hipGetLastError();
 }
