@@ -154,6 +154,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   const int m0 = blockIdx.y * a.qa;
   const int nqa = min(a.qa, a.Nq - m0);
   const int nq8 = (nqa + 7) & ~7;
+  const int nq4 = (nqa + 3) & ~3;
   const double qs = a.q0 + m0 * a.dq;
   const double dq = a.dq;
   const int64_t pidx = static_cast<int64_t>(blockIdx.y) * a.n_strips + t;
@@ -267,35 +268,44 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
           asm volatile("" : "+v"(nla), "+v"(nlb));
           float a1e = 0.f, a1o = 0.f, a2e = 0.f, a2o = 0.f, a3e = 0.f, a3o = 0.f;
           float b1e = 0.f, b1o = 0.f, b2e = 0.f, b2o = 0.f, b3e = 0.f, b3o = 0.f;
+          // one even and one odd q step of both atoms
+          auto two_steps = [&](float ue, float ve, float uo, float vo) {
+            a1e = fmaf(ue, da, a1e);
+            b1e = fmaf(ue, db, b1e);
+            a2e = fmaf(ue, za, a2e);
+            b2e = fmaf(ue, zb, b2e);
+            a3e = fmaf(ve, za, a3e);
+            b3e = fmaf(ve, zb, b3e);
+            za += da;
+            zb += db;
+            da = fmaf(nla, za, da);
+            db = fmaf(nlb, zb, db);
+            a1o = fmaf(uo, da, a1o);
+            b1o = fmaf(uo, db, b1o);
+            a2o = fmaf(uo, za, a2o);
+            b2o = fmaf(uo, zb, b2o);
+            a3o = fmaf(vo, za, a3o);
+            b3o = fmaf(vo, zb, b3o);
+            za += da;
+            zb += db;
+            da = fmaf(nla, za, da);
+            db = fmaf(nlb, zb, db);
+          };
+          // blocks of 8 q, then a block of 4 if the chunk's count (rounded
+          // up to 4) leaves one: no steps past the chunk's last 4
 #pragma unroll 1
-          for (int m = 0; m < nq8; m += 8) {
+          for (int m = 0; m + 8 <= nq4; m += 8) {
             const float4 ua = ul4[m >> 2], ub = ul4[(m >> 2) + 1];
             const float4 va = vl4[m >> 2], vb = vl4[(m >> 2) + 1];
-            const float uu[8] = {ua.x, ua.y, ua.z, ua.w, ub.x, ub.y, ub.z, ub.w};
-            const float vv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
-#pragma unroll
-            for (int s = 0; s < 8; s += 2) {
-              a1e = fmaf(uu[s], da, a1e);
-              b1e = fmaf(uu[s], db, b1e);
-              a2e = fmaf(uu[s], za, a2e);
-              b2e = fmaf(uu[s], zb, b2e);
-              a3e = fmaf(vv[s], za, a3e);
-              b3e = fmaf(vv[s], zb, b3e);
-              za += da;
-              zb += db;
-              da = fmaf(nla, za, da);
-              db = fmaf(nlb, zb, db);
-              a1o = fmaf(uu[s + 1], da, a1o);
-              b1o = fmaf(uu[s + 1], db, b1o);
-              a2o = fmaf(uu[s + 1], za, a2o);
-              b2o = fmaf(uu[s + 1], zb, b2o);
-              a3o = fmaf(vv[s + 1], za, a3o);
-              b3o = fmaf(vv[s + 1], zb, b3o);
-              za += da;
-              zb += db;
-              da = fmaf(nla, za, da);
-              db = fmaf(nlb, zb, db);
-            }
+            two_steps(ua.x, va.x, ua.y, va.y);
+            two_steps(ua.z, va.z, ua.w, va.w);
+            two_steps(ub.x, vb.x, ub.y, vb.y);
+            two_steps(ub.z, vb.z, ub.w, vb.w);
+          }
+          if (nq4 & 4) {
+            const float4 ua = ul4[(nq4 - 4) >> 2], va = vl4[(nq4 - 4) >> 2];
+            two_steps(ua.x, va.x, ua.y, va.y);
+            two_steps(ua.z, va.z, ua.w, va.w);
           }
           const double GA = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, u0);
           const double GB = adj_force(B, b1e, b1o, b2e, b2o, b3e, b3o, dq, u0);
