@@ -244,12 +244,14 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   sc.geo.ib = sas::kWave;
   sc.geo.c = bj / sas::kWave;
   // strips of g J blocks: g = 1 unless the partial rows (with the table
-  // gradient's T rows per strip) would exceed 256 MiB
+  // gradient's T rows per strip) would exceed 2 GiB (longer strips halve the
+  // work-groups and lengthen the last round: the rod's table gradient ran 7%
+  // slower with g = 2 under a 256 MiB bound)
   for (int32_t g = 1;; g *= 2) {
     sc.geo.g = g;
     int64_t strips = 0;
     for (int64_t n : sizes) strips += sas::strips_of(n, sc.geo);
-    if (static_cast<double>(strips) * Nq * 8.0 * (1 + tg_types) <= 256.0 * 1024 * 1024 || g >= 1024) break;
+    if (static_cast<double>(strips) * Nq * 8.0 * (1 + tg_types) <= 2048.0 * 1024 * 1024 || g >= 1024) break;
   }
   // execution order: largest structure first (longest-processing-time order)
   std::vector<int32_t> order(sc.S);
