@@ -143,25 +143,16 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
         const PairSeed B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
         asm volatile("" ::: "memory");
         float za = A.z, da = A.d, zb = B.z, db = B.d;
-        // (the negated lambdas are laundered through an empty asm: known to be
-        // negations, they would be folded into a source modifier, which needs the
-        // 64-bit VOP3 encoding of the FMA; a plain register operand keeps the 32-bit
-        // v_fmac form, which issues faster on gfx950)
-        float nla = A.nlam, nlb = B.nlam;
-        asm volatile("" : "+v"(nla), "+v"(nlb));
+        // (fixed registers, banks chosen so that no step instruction reads three
+        // operands from one bank; the negated lambdas are plain register
+        // operands, so the FMAs keep the 32-bit v_fmac encoding)
+        constexpr int kPin = pin_base(QC > 128 ? 2 : 3, QC <= 32);
 #pragma unroll
         for (int m = 0; m < QC; ++m) {
-          if (m & 1) {
-            acc[m] = fmaf(A.sg, za, acc[m]);
-            acc[m] = fmaf(B.sg, zb, acc[m]);
-          } else {
-            acc[m] += za;
-            acc[m] += zb;
-          }
-          za += da;
-          zb += db;
-          da = fmaf(nla, za, da);
-          db = fmaf(nlb, zb, db);
+          if (m & 1)
+            rec_step2<kPin, true>(acc[m], za, zb, da, db, A.sg, B.sg, A.nlam, B.nlam);
+          else
+            rec_step2<kPin, false>(acc[m], za, zb, da, db, A.sg, B.sg, A.nlam, B.nlam);
         }
       }
       }
