@@ -406,14 +406,13 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
             *reinterpret_cast<const float4*>(a.tabp + static_cast<int64_t>(tr) * a.ldt + m0 + 4 * c);
       }
       __syncthreads();
+      if constexpr (DIRECT) {
 #pragma unroll 1
-      for (int jl = u0; jl < u0 + ns; ++jl) {
-        asm volatile("" ::: "memory");
-        const double4 pj = sj[jl - u0];
-        const float* f = fj[jl - u0];
-        const bool use = vi && jl > i;
-        double cx, cy, cz;
-        if constexpr (DIRECT) {
+        for (int jl = u0; jl < u0 + ns; ++jl) {
+          asm volatile("" ::: "memory");
+          const double4 pj = sj[jl - u0];
+          const float* f = fj[jl - u0];
+          const bool use = vi && jl > i;
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           const double ir = rsqrt_f64(fmax(r2, 1e-60));
@@ -428,46 +427,95 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
             ss = fmaf(u * iql[m], e.s, ss);
           }
           const double G = adj_force_direct(use && r2 > 0.0, ir, cc, ss);
-          cx = G * dx;
-          cy = G * dy;
-          cz = G * dz;
-        } else {
-          const AdjSeed A = adj_seed(pi, pj, use, dq, qs);
-          float z = A.z, dd = A.d;
-          float nl = A.nlam;  // laundered, as in k_adjoint
-          asm volatile("" : "+v"(nl));
+          const double cx = G * dx, cy = G * dy, cz = G * dz;
+          gx += cx;
+          gy += cy;
+          gz += cz;
+          const float sx = wave_total(static_cast<float>(cx));
+          const float sy = wave_total(static_cast<float>(cy));
+          const float sz = wave_total(static_cast<float>(cz));
+          if (lane == 0) {
+            double* gj = gjl + 3 * (jl - j0);
+            gj[0] -= sx;
+            gj[1] -= sy;
+            gj[2] -= sz;
+          }
+        }
+      } else {
+        // two pairs (j, j+1) per iteration sharing the lane's weights and 1/q:
+        // two independent recurrence chains for the scheduler to interleave; an
+        // odd run ends with a masked partner (zero seeds, zero force)
+#pragma unroll 1
+        for (int jl = u0; jl < u0 + ns; jl += 2) {
+          const bool two = jl + 1 < u0 + ns;
+          const int jb = two ? jl + 1 : jl;
+          const AdjSeed A = adj_seed(pi, sj[jl - u0], vi && jl > i, dq, qs);
+          asm volatile("" ::: "memory");
+          const AdjSeed B = adj_seed(pi, sj[jb - u0], vi && jb > i && two, dq, qs);
+          asm volatile("" ::: "memory");
+          const float* fa = fj[jl - u0];
+          const float* fb = fj[jb - u0];
+          float za = A.z, da = A.d, zb = B.z, db = B.d;
+          float nla = A.nlam, nlb = B.nlam;  // laundered, as in k_adjoint
+          asm volatile("" : "+v"(nla), "+v"(nlb));
           float a1e = 0.f, a1o = 0.f, a2e = 0.f, a2o = 0.f, a3e = 0.f, a3o = 0.f;
+          float b1e = 0.f, b1o = 0.f, b2e = 0.f, b2o = 0.f, b3e = 0.f, b3o = 0.f;
 #pragma unroll
           for (int m = 0; m < QA; m += 2) {
-            const float ue = wi[m] * f[m], ve = ue * iql[m];
-            a1e = fmaf(ue, dd, a1e);
-            a2e = fmaf(ue, z, a2e);
-            a3e = fmaf(ve, z, a3e);
-            z += dd;
-            dd = fmaf(nl, z, dd);
-            const float uo = wi[m + 1] * f[m + 1], vo = uo * iql[m + 1];
-            a1o = fmaf(uo, dd, a1o);
-            a2o = fmaf(uo, z, a2o);
-            a3o = fmaf(vo, z, a3o);
-            z += dd;
-            dd = fmaf(nl, z, dd);
+            const float iqe = iql[m], iqo = iql[m + 1];
+            const float uae = wi[m] * fa[m], ube = wi[m] * fb[m];
+            const float vae = uae * iqe, vbe = ube * iqe;
+            a1e = fmaf(uae, da, a1e);
+            b1e = fmaf(ube, db, b1e);
+            a2e = fmaf(uae, za, a2e);
+            b2e = fmaf(ube, zb, b2e);
+            a3e = fmaf(vae, za, a3e);
+            b3e = fmaf(vbe, zb, b3e);
+            za += da;
+            zb += db;
+            da = fmaf(nla, za, da);
+            db = fmaf(nlb, zb, db);
+            const float uao = wi[m + 1] * fa[m + 1], ubo = wi[m + 1] * fb[m + 1];
+            const float vao = uao * iqo, vbo = ubo * iqo;
+            a1o = fmaf(uao, da, a1o);
+            b1o = fmaf(ubo, db, b1o);
+            a2o = fmaf(uao, za, a2o);
+            b2o = fmaf(ubo, zb, b2o);
+            a3o = fmaf(vao, za, a3o);
+            b3o = fmaf(vbo, zb, b3o);
+            za += da;
+            zb += db;
+            da = fmaf(nla, za, da);
+            db = fmaf(nlb, zb, db);
           }
-          const double G = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, wi[0] * f[0]);
-          cx = G * A.dx;
-          cy = G * A.dy;
-          cz = G * A.dz;
-        }
-        gx += cx;
-        gy += cy;
-        gz += cz;
-        const float sx = wave_total(static_cast<float>(cx));
-        const float sy = wave_total(static_cast<float>(cy));
-        const float sz = wave_total(static_cast<float>(cz));
-        if (lane == 0) {
-          double* gj = gjl + 3 * (jl - j0);
-          gj[0] -= sx;
-          gj[1] -= sy;
-          gj[2] -= sz;
+          const double GA = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, wi[0] * fa[0]);
+          const double GB = adj_force(B, b1e, b1o, b2e, b2o, b3e, b3o, dq, wi[0] * fb[0]);
+          const double cax = GA * A.dx, cay = GA * A.dy, caz = GA * A.dz;
+          const double cbx = GB * B.dx, cby = GB * B.dy, cbz = GB * B.dz;
+          gx += cax;
+          gy += cay;
+          gz += caz;
+          gx += cbx;
+          gy += cby;
+          gz += cbz;
+          const float sax = wave_total(static_cast<float>(cax));
+          const float say = wave_total(static_cast<float>(cay));
+          const float saz = wave_total(static_cast<float>(caz));
+          const float sbx = wave_total(static_cast<float>(cbx));
+          const float sby = wave_total(static_cast<float>(cby));
+          const float sbz = wave_total(static_cast<float>(cbz));
+          if (lane == 0) {
+            double* ga = gjl + 3 * (jl - j0);
+            ga[0] -= sax;
+            ga[1] -= say;
+            ga[2] -= saz;
+            if (two) {
+              double* gb = gjl + 3 * (jb - j0);
+              gb[0] -= sbx;
+              gb[1] -= sby;
+              gb[2] -= sbz;
+            }
+          }
         }
       }
     }
