@@ -575,6 +575,7 @@ bool adjoint_bj_supported(int32_t bj) { return bj == 128 || bj == 256; }
 
 hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st) {
   if (a.n_strips <= 0) return hipSuccess;
+  if (!geometry_ok(a.geo) || a.geo.ib != 2 * kWave || a.geo.g != 1) return hipErrorInvalidValue;
   const dim3 grid(static_cast<uint32_t>(a.n_strips), nchunks);
   switch (a.geo.bj) {
     case 128:
@@ -596,7 +597,8 @@ hipError_t launch_adjoint(const AdjArgs& a, int32_t nchunks, hipStream_t st) {
 
 hipError_t launch_adjoint_pa(const AdjArgs& a, int32_t nchunks, int32_t qa_template, hipStream_t st) {
   if (a.n_strips <= 0) return hipSuccess;
-  if (a.geo.bj != kAdjPaBJ || a.geo.ib != kWave || a.qa > qa_template) return hipErrorInvalidValue;
+  if (!geometry_ok(a.geo) || a.geo.bj != kAdjPaBJ || a.geo.ib != kWave || a.geo.g != 1 || a.qa > qa_template)
+    return hipErrorInvalidValue;
   const dim3 grid(static_cast<uint32_t>(a.n_strips), nchunks);
   if (a.qdev) {
     if (qa_template != 64) return hipErrorInvalidValue;
@@ -615,6 +617,7 @@ hipError_t launch_adjoint_pa(const AdjArgs& a, int32_t nchunks, int32_t qa_templ
 hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, const int32_t* perm, double* grad_out,
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (!geometry_ok(a.geo)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_grad_reduce, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, a, nchunks, perm,
                      grad_out);
   return hipGetLastError();

@@ -200,6 +200,7 @@ bool direct_qc_supported(int32_t qc) { return qc == 32; }
 
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st) {
   if (n_strips_total <= 0) return hipSuccess;
+  if (!geometry_ok(a.geo)) return hipErrorInvalidValue;
   const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
   const dim3 grid(static_cast<uint32_t>(n_strips_total), nchunks);
   if (a.qdev) {

@@ -42,6 +42,13 @@ struct Geometry {
   int32_t ib;  // atoms per I block (64 forward: one per lane; 128 adjoint: two per lane)
 };
 
+// The strip decode and the walks over a row and a column of strips assume J
+// blocks made of whole I blocks (bj = c ib); a geometry that breaks this would
+// send them past the strip rows, so the launchers refuse it.
+inline bool geometry_ok(const Geometry& g) {
+  return g.ib > 0 && g.bj > 0 && g.g > 0 && g.bj % g.ib == 0 && g.c == g.bj / g.ib;
+}
+
 struct ForwardArgs {
   DescView sd;
   Geometry geo;

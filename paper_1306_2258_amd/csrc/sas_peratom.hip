@@ -276,6 +276,7 @@ hipError_t launch_atom_sums(const DescView& sd, int64_t n_pack_blocks, const int
 
 template <bool ROWS>
 hipError_t launch_forward_pa_t(const ForwardArgs& a, dim3 grid, int32_t qc_template, hipStream_t st) {
+  if (!geometry_ok(a.geo)) return hipErrorInvalidValue;
   if (a.qdev) {
     if (qc_template != 32) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_forward_pa<32, true, ROWS>), grid, dim3(kWave), 0, st, a);
