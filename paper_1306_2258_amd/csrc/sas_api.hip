@@ -72,6 +72,11 @@ struct sas_ctx {
   // each call (a synchronisation each); four counters on the device
   bool debug_validate = false;
   unsigned long long* dbg = nullptr;
+  // hybrid profiles: a second stream (default priority) for the direct part,
+  // which runs beside the orientation average, and the events that fork it
+  // from and join it back into the caller's stream
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -741,6 +746,12 @@ void sas_destroy(sas_ctx* ctx) {
     }
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->dbg) (void)hipFree(ctx->dbg);
+    if (ctx->side) {
+      (void)hipStreamSynchronize(ctx->side);
+      (void)hipStreamDestroy(ctx->side);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   }
   delete ctx;
 }
@@ -1583,6 +1594,33 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
     nq_o = std::max(0, ((nq_o - 1) / sas::kOrientQ) * sas::kOrientQ);  // drop the last chunk
   }
 
+  // the direct part runs on the context's second stream beside the
+  // orientation average (disjoint q ranges, workspace regions and outputs),
+  // forked from the caller's stream and joined back into it on every exit
+  const int32_t nq_d = nq - nq_o;
+  hipStream_t hd = hs;
+  struct Join {
+    hipStream_t from = nullptr, into = nullptr;
+    hipEvent_t ev = nullptr;
+    ~Join() {
+      if (ev) {
+        (void)hipEventRecord(ev, from);
+        (void)hipStreamWaitEvent(into, ev, 0);
+      }
+    }
+  } join;
+  if (nq_o > 0 && nq_d > 0) {
+    if (!ctx->side) SAS_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    if (!ctx->fork_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    if (!ctx->join_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
+    hd = ctx->side;
+    SAS_HIP(hipEventRecord(ctx->fork_ev, hs));
+    SAS_HIP(hipStreamWaitEvent(hd, ctx->fork_ev, 0));
+    join.from = hd;
+    join.into = hs;
+    join.ev = ctx->join_ev;
+  }
+
   // 3. orientation average of the leading q values
   if (nq_o > 0) {
     std::vector<char> img(L.upload_bytes, 0);
@@ -1613,20 +1651,19 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   }
 
   // 4. direct sum for the rest, on a compact copy of their table columns
-  const int32_t nq_d = nq - nq_o;
   if (nq_d > 0) {
     QGrid gd;
     st = classify_q(q + nq_o, nq_d, &gd);
     if (st != SAS_OK) return st;
     float* tabd = reinterpret_cast<float*>(w + L.tabd);
-    SAS_HIP(sas::launch_copy_cols(table, t, nq, nq_o, nq_d, nq_d, tabd, hs));
+    SAS_HIP(sas::launch_copy_cols(table, t, nq, nq_o, nq_d, nq_d, tabd, hd));
     const Schedule sd = make_schedule(ctx, std::vector<int64_t>{n}, t, nq_d, 0, 0, !gd.uniform || ctx->force_direct,
                                       use_per_atom(ctx, t, n));
     const Layout Ld = make_layout(sd, t, nq_d);
     void* wd = w + L.direct;
-    st = stage_upload(ctx, wd, Ld, upload_image(sd, Ld, gd), hs);
+    st = stage_upload(ctx, wd, Ld, upload_image(sd, Ld, gd), hd);
     if (st != SAS_OK) return st;
-    st = enqueue_forward(ctx, sd, Ld, coords, types, tabd, t, nq_d, gd.q0, gd.dq, I_out + nq_o, wd, hs);
+    st = enqueue_forward(ctx, sd, Ld, coords, types, tabd, t, nq_d, gd.q0, gd.dq, I_out + nq_o, wd, hd);
     if (st != SAS_OK) return st;
   }
   if (n_orient) *n_orient = nq_o;

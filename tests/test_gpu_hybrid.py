@@ -154,6 +154,32 @@ def test_hybrid_auto_globular(sd, q1):
     assert err.max() <= TOL
 
 
+def test_hybrid_split_runs_beside_and_joins(sd):
+    """With both parts non-empty (the 20,000-atom globule on [0, 1] splits)
+    the direct part runs on a second stream beside the orientation average:
+    a copy queued on the caller's stream right after each call sees the whole
+    profile (the join), bitwise equal to a call on the default stream."""
+    import torch
+
+    say("hybrid split on a side stream, joined into the caller's stream")
+    m = _globule(20000, W.q_grid(0.0, 1.0, 100), 13062258 + 60)
+    c, t, tab = to_dev(m)
+    ref, n_ref = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
+    print(f"averaged q values: {n_ref}")
+    assert 0 < n_ref < len(m.q)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    copies = []
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            I, n_o = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
+            assert n_o == n_ref
+            copies.append(I.clone())
+    torch.cuda.synchronize()
+    for J in copies:
+        assert torch.equal(J, ref)
+
+
 def test_hybrid_small_workspace(sd):
     """With a workspace too small for the averaged part the automatic mode
     averages fewer q values (still exact where it sums directly); the
