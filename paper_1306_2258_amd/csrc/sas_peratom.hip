@@ -191,24 +191,40 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           asm volatile("" ::: "memory");
           const PairSeed B = pair_seed(pi, sj[jb - u0], vi && (ROWS ? jb != i : jb > i) && two, dq, qs);
           asm volatile("" ::: "memory");
-          const float* fa = fj[jl - u0];
-          const float* fb = fj[jb - u0];
+          const float4* fa4 = reinterpret_cast<const float4*>(fj[jl - u0]);
+          const float4* fb4 = reinterpret_cast<const float4*>(fj[jb - u0]);
           float za = A.z, da = A.d, zb = B.z, db = B.d;
           float nla = A.nlam, nlb = B.nlam;  // laundered: see the type-segment form
           asm volatile("" : "+v"(nla), "+v"(nlb));
+          // the rows' values for each 4 q steps are loaded one group ahead,
+          // so the LDS latency overlaps the previous group's steps
+          float4 ca = fa4[0], cb = fb4[0];
 #pragma unroll
-          for (int m = 0; m < QC; ++m) {
-            if (m & 1) {
-              acc[m] = fmaf(fa[m] * A.sg, za, acc[m]);
-              acc[m] = fmaf(fb[m] * B.sg, zb, acc[m]);
-            } else {
-              acc[m] = fmaf(fa[m], za, acc[m]);
-              acc[m] = fmaf(fb[m], zb, acc[m]);
+          for (int g4 = 0; g4 < QC / 4; ++g4) {
+            float4 na = ca, nb = cb;
+            if (g4 + 1 < QC / 4) {
+              na = fa4[g4 + 1];
+              nb = fb4[g4 + 1];
             }
-            za += da;
-            zb += db;
-            da = fmaf(nla, za, da);
-            db = fmaf(nlb, zb, db);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads issued here
+            const float fav[4] = {ca.x, ca.y, ca.z, ca.w}, fbv[4] = {cb.x, cb.y, cb.z, cb.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int m = 4 * g4 + k;
+              if (m & 1) {
+                acc[m] = fmaf(fav[k] * A.sg, za, acc[m]);
+                acc[m] = fmaf(fbv[k] * B.sg, zb, acc[m]);
+              } else {
+                acc[m] = fmaf(fav[k], za, acc[m]);
+                acc[m] = fmaf(fbv[k], zb, acc[m]);
+              }
+              za += da;
+              zb += db;
+              da = fmaf(nla, za, da);
+              db = fmaf(nlb, zb, db);
+            }
+            ca = na;
+            cb = nb;
           }
         }
       }
