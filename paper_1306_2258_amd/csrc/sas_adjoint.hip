@@ -460,33 +460,55 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
           asm volatile("" : "+v"(nla), "+v"(nlb));
           float a1e = 0.f, a1o = 0.f, a2e = 0.f, a2o = 0.f, a3e = 0.f, a3o = 0.f;
           float b1e = 0.f, b1o = 0.f, b2e = 0.f, b2o = 0.f, b3e = 0.f, b3o = 0.f;
+          // the rows' values and 1/q for each 4 q steps are loaded one group
+          // ahead, so the LDS latency overlaps the previous group's steps
+          const float4* fa4 = reinterpret_cast<const float4*>(fa);
+          const float4* fb4 = reinterpret_cast<const float4*>(fb);
+          const float4* iq4 = reinterpret_cast<const float4*>(iql);
+          float4 ca = fa4[0], cb = fb4[0], ci = iq4[0];
 #pragma unroll
-          for (int m = 0; m < QA; m += 2) {
-            const float iqe = iql[m], iqo = iql[m + 1];
-            const float uae = wi[m] * fa[m], ube = wi[m] * fb[m];
-            const float vae = uae * iqe, vbe = ube * iqe;
-            a1e = fmaf(uae, da, a1e);
-            b1e = fmaf(ube, db, b1e);
-            a2e = fmaf(uae, za, a2e);
-            b2e = fmaf(ube, zb, b2e);
-            a3e = fmaf(vae, za, a3e);
-            b3e = fmaf(vbe, zb, b3e);
-            za += da;
-            zb += db;
-            da = fmaf(nla, za, da);
-            db = fmaf(nlb, zb, db);
-            const float uao = wi[m + 1] * fa[m + 1], ubo = wi[m + 1] * fb[m + 1];
-            const float vao = uao * iqo, vbo = ubo * iqo;
-            a1o = fmaf(uao, da, a1o);
-            b1o = fmaf(ubo, db, b1o);
-            a2o = fmaf(uao, za, a2o);
-            b2o = fmaf(ubo, zb, b2o);
-            a3o = fmaf(vao, za, a3o);
-            b3o = fmaf(vbo, zb, b3o);
-            za += da;
-            zb += db;
-            da = fmaf(nla, za, da);
-            db = fmaf(nlb, zb, db);
+          for (int g4 = 0; g4 < QA / 4; ++g4) {
+            float4 na = ca, nb = cb, ni = ci;
+            if (g4 + 1 < QA / 4) {
+              na = fa4[g4 + 1];
+              nb = fb4[g4 + 1];
+              ni = iq4[g4 + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads issued here
+            const float fav[4] = {ca.x, ca.y, ca.z, ca.w}, fbv[4] = {cb.x, cb.y, cb.z, cb.w};
+            const float iqv[4] = {ci.x, ci.y, ci.z, ci.w};
+#pragma unroll
+            for (int k = 0; k < 4; k += 2) {
+              const int m = 4 * g4 + k;
+              const float iqe = iqv[k], iqo = iqv[k + 1];
+              const float uae = wi[m] * fav[k], ube = wi[m] * fbv[k];
+              const float vae = uae * iqe, vbe = ube * iqe;
+              a1e = fmaf(uae, da, a1e);
+              b1e = fmaf(ube, db, b1e);
+              a2e = fmaf(uae, za, a2e);
+              b2e = fmaf(ube, zb, b2e);
+              a3e = fmaf(vae, za, a3e);
+              b3e = fmaf(vbe, zb, b3e);
+              za += da;
+              zb += db;
+              da = fmaf(nla, za, da);
+              db = fmaf(nlb, zb, db);
+              const float uao = wi[m + 1] * fav[k + 1], ubo = wi[m + 1] * fbv[k + 1];
+              const float vao = uao * iqo, vbo = ubo * iqo;
+              a1o = fmaf(uao, da, a1o);
+              b1o = fmaf(ubo, db, b1o);
+              a2o = fmaf(uao, za, a2o);
+              b2o = fmaf(ubo, zb, b2o);
+              a3o = fmaf(vao, za, a3o);
+              b3o = fmaf(vbo, zb, b3o);
+              za += da;
+              zb += db;
+              da = fmaf(nla, za, da);
+              db = fmaf(nlb, zb, db);
+            }
+            ca = na;
+            cb = nb;
+            ci = ni;
           }
           const double GA = adj_force(A, a1e, a1o, a2e, a2o, a3e, a3o, dq, wi[0] * fa[0]);
           const double GB = adj_force(B, b1e, b1o, b2e, b2o, b3e, b3o, dq, wi[0] * fb[0]);
