@@ -132,16 +132,38 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
       // two atom pairs (j, j+1) per iteration: two independent recurrence
       // chains give the scheduler work to issue while either waits on its
       // previous result; an odd segment ends with a masked partner
+      // (the two-wave kernels, whose q steps leave registers free, load the
+      // next two pairs' coordinates while the current pairs' steps run; the
+      // three-wave kernels have none to spare and read them just before use)
+      constexpr bool kAhead = QC > 128;
+      double4 pja{}, pjb{};
+      if constexpr (kAhead) {
+        pja = sj[sa - j0];
+        pjb = sj[(sa + 1 < sb ? sa + 1 : sa) - j0];
+      }
 #pragma unroll 1
       for (int jl = sa; jl < sb; jl += 2) {
         const int jb = jl + 1 < sb ? jl + 1 : jl;
         // (empty volatile asm: a scheduling boundary, so the two FP64 set-ups
         // run one after the other and their temporaries never coexist with
         // each other and the QC accumulators)
-        const PairSeed A = pair_seed(pi, sj[jl - j0], on && jl > i, dq, qs);
-        asm volatile("" ::: "memory");
-        const PairSeed B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
-        asm volatile("" ::: "memory");
+        PairSeed A, B;
+        if constexpr (kAhead) {
+          A = pair_seed(pi, pja, on && jl > i, dq, qs);
+          asm volatile("" ::: "memory");
+          B = pair_seed(pi, pjb, on && jb > i && jl + 1 < sb, dq, qs);
+          asm volatile("" ::: "memory");
+          const int jn = jl + 2 < sb ? jl + 2 : jl;
+          const int jnb = jn + 1 < sb ? jn + 1 : jn;
+          pja = sj[jn - j0];
+          pjb = sj[jnb - j0];
+          __builtin_amdgcn_sched_barrier(0);  // keep the loads issued here
+        } else {
+          A = pair_seed(pi, sj[jl - j0], on && jl > i, dq, qs);
+          asm volatile("" ::: "memory");
+          B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
+          asm volatile("" ::: "memory");
+        }
         float za = A.z, da = A.d, zb = B.z, db = B.d;
         // (fixed registers, banks chosen so that no step instruction reads three
         // operands from one bank; the negated lambdas are plain register
