@@ -236,7 +236,12 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
  * (the amplitude sums take each atom's own row; no type sort).  This
  * call synchronises `stream` once (it reads the molecule's radius back to
  * choose L).  If the workspace is smaller than the query returns, fewer q
- * values are averaged (AUTO) or the call fails (ORIENT_ALL).
+ * values are averaged (AUTO) or the call fails (ORIENT_ALL).  When both
+ * parts are non-empty the direct part runs on a second stream owned by the
+ * context, beside the averaged part; it is forked from `stream` and joined
+ * back into it before the call returns, so work queued on `stream` after the
+ * call sees the whole profile.  Two hybrid calls on one context must not
+ * be made from different threads at the same time: they share that stream.
  */
 #define SAS_HYBRID_AUTO 0
 #define SAS_HYBRID_ORIENT_ALL 1
