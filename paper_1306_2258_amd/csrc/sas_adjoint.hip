@@ -291,9 +291,10 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
             da = fmaf(nla, za, da);
             db = fmaf(nlb, zb, db);
           };
-          // blocks of 8 q, then a block of 4 if the chunk's count (rounded
-          // up to 4) leaves one: no steps past the chunk's last 4
-#pragma unroll 1
+          // blocks of 8 q (the loop unrolled twice: one branch per 16 q),
+          // then a block of 4 if the chunk's count (rounded up to 4) leaves
+          // one: no steps past the chunk's last 4
+#pragma unroll 2
           for (int m = 0; m + 8 <= nq4; m += 8) {
             const float4 ua = ul4[m >> 2], ub = ul4[(m >> 2) + 1];
             const float4 va = vl4[m >> 2], vb = vl4[(m >> 2) + 1];
