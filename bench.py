@@ -471,8 +471,37 @@ def bench_hybrid(sd, W, torch, dev):
     ms_hybrid = _time(lambda: sd.debye_profile_hybrid(coords, types, table, m.q, tol=1e-9, ctx=ctx), torch)
     diff = float(((I - direct).abs() / direct.abs()).max())
     log(f"hybrid {ms_hybrid:.3f} ms ({n_o} q averaged) vs direct {ms_direct:.3f} ms, max rel diff {diff:.2e}")
-    return {"atoms": m.n, "nq": len(m.q), "q_averaged": n_o, "ms_direct": ms_direct, "ms_hybrid": ms_hybrid,
-            "speedup": ms_direct / ms_hybrid, "max_rel_diff": diff}
+    out = {"atoms": m.n, "nq": len(m.q), "q_averaged": n_o, "ms_direct": ms_direct, "ms_hybrid": ms_hybrid,
+           "speedup": ms_direct / ms_hybrid, "max_rel_diff": diff}
+    out["split"] = bench_hybrid_split(sd, W, torch, dev, ctx)
+    return out
+
+
+def bench_hybrid_split(sd, W, torch, dev, ctx):
+    """A 20,000-atom globule on 100 q in [0, 1], where the hybrid averages a
+    prefix and sums the rest directly on a second stream: the call against
+    the two parts run alone and against the direct sum of every q."""
+    m = W.globular(20000, nq=100)
+    coords = torch.from_numpy(m.coords).to(dev)
+    types = torch.from_numpy(m.types).to(dev)
+    table = torch.from_numpy(m.table).to(dev)
+    direct = sd.debye_profile(coords, types, table, m.q, ctx=ctx).clone()
+    ms_direct = _time(lambda: sd.debye_profile(coords, types, table, m.q, ctx=ctx), torch)
+    I, n_o = sd.debye_profile_hybrid(coords, types, table, m.q, tol=1e-9, ctx=ctx)
+    ms_hybrid = _time(lambda: sd.debye_profile_hybrid(coords, types, table, m.q, tol=1e-9, ctx=ctx), torch)
+    diff = float(((I - direct).abs() / direct.abs()).max())
+    res = {"atoms": m.n, "nq": len(m.q), "q_averaged": n_o, "ms_hybrid": ms_hybrid, "ms_direct": ms_direct,
+           "max_rel_diff": diff}
+    if 0 < n_o < len(m.q):
+        qo, qd = np.ascontiguousarray(m.q[:n_o]), np.ascontiguousarray(m.q[n_o:])
+        to, td = table[:, :n_o].contiguous(), table[:, n_o:].contiguous()
+        res["ms_orient_part_alone"] = _time(
+            lambda: sd.debye_profile_hybrid(coords, types, to, qo, tol=1e-9, mode="orient", ctx=ctx), torch)
+        res["ms_direct_part_alone"] = _time(lambda: sd.debye_profile(coords, types, td, qd, ctx=ctx), torch)
+    log(f"hybrid split: {n_o} of {len(m.q)} q averaged, {ms_hybrid:.3f} ms vs direct {ms_direct:.3f} ms"
+        + (f" (parts alone {res['ms_orient_part_alone']:.3f} + {res['ms_direct_part_alone']:.3f} ms)"
+           if "ms_orient_part_alone" in res else ""))
+    return res
 
 
 def bench_grad(sd, W, torch, dev):

@@ -1282,10 +1282,13 @@ constexpr int64_t kOrientBlocksTarget = 16384;         // most work-groups the a
 // Time per unit, in pair*q steps of the type-form recurrence (measured on
 // MI355X): the per-pair set-up of the recurrence (about 66 steps), a step of
 // the direct form (4.3) and its set-up (5), and an atom*direction*q of the
-// orientation kernel with a sine and cosine per q (9) or with the rotation
-// walk (5; the kernel alone runs 1.8x faster).
-constexpr double kSetupRecurrence = 66.0, kStepDirect = 4.3, kSetupDirect = 5.0, kCostOrient = 9.0,
-                 kCostOrientRot = 5.0;
+// orientation average with the rotation walk (6.5: whole calls on globules
+// gave 6.2 at 50,000 atoms and 7.6 at 20,000) or with a sine and cosine per q
+// (1.8x that, the kernels' ratio), plus a fixed cost of the averaged part
+// (the radius read back and the host's quadrature plan, about 0.1 ms, 2.2e9
+// steps), which keeps small molecules on the direct sum.
+constexpr double kSetupRecurrence = 66.0, kStepDirect = 4.3, kSetupDirect = 5.0, kCostOrient = 11.7,
+                 kCostOrientRot = 6.5, kCostOrientFixed = 2.2e9;
 
 // The orientation kernel walks exp(i q p) over the leading nq_o q values when
 // they form a uniform grid whose step *dq turns the farthest atom's phase by
@@ -1477,12 +1480,16 @@ size_t orient_bound_bytes(int64_t n, int32_t t, int32_t nq, int64_t cap) {
   return b;
 }
 
-// Directions per chunk the automatic split can choose: an averaged q must cost
-// less than the direct steps it saves (at most twice a step, with padding).
+// Directions per chunk the automatic split can choose: an averaged q may cost
+// up to 2.6 direct steps of the q it replaces (twice a step for padding, and
+// 1.3 for the recurrence's set-up, which the direct sum spreads over its q
+// values: without it the 50,000-atom globule's last chunks on [0, 1] would be
+// refused although averaging every q is the faster choice there).  The
+// workspace query bounds the averaged part by the same cap.
 int64_t orient_cap(int64_t n, int32_t mode, bool uniform, bool rot) {
   if (mode == SAS_HYBRID_ORIENT_ALL) return kOrientCapAll;
   const double step = uniform ? 1.0 : kStepDirect;
-  return std::max<int64_t>(1, static_cast<int64_t>(static_cast<double>(std::max<int64_t>(n - 1, 0)) * step /
+  return std::max<int64_t>(1, static_cast<int64_t>(static_cast<double>(std::max<int64_t>(n - 1, 0)) * step * 1.3 /
                                                    (rot ? kCostOrientRot : kCostOrient)));
 }
 
@@ -1563,7 +1570,7 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
       const int32_t m1 = std::min(nq, m0 + sas::kOrientQ);
       const int64_t L = orient_degree(q[m1 - 1], r_max, tol);
       units += static_cast<double>(L + 1) * (2 * L + 1) * (m1 - m0) * static_cast<double>(n);
-      orient = units * (orient_rot(q, m1, r_max, nullptr) ? kCostOrientRot : kCostOrient);
+      orient = kCostOrientFixed + units * (orient_rot(q, m1, r_max, nullptr) ? kCostOrientRot : kCostOrient);
       QGrid rest;
       const bool uni = m1 < nq && classify_q(q + m1, nq - m1, &rest) == SAS_OK && rest.uniform;
       const double total = orient + pairs * direct_steps(nq - m1, uni);

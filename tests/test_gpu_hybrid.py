@@ -155,17 +155,22 @@ def test_hybrid_auto_globular(sd, q1):
 
 
 def test_hybrid_split_runs_beside_and_joins(sd):
-    """With both parts non-empty (the 20,000-atom globule on [0, 1] splits)
-    the direct part runs on a second stream beside the orientation average:
-    a copy queued on the caller's stream right after each call sees the whole
-    profile (the join), bitwise equal to a call on the default stream."""
+    """With both parts non-empty the direct part runs on a second stream
+    beside the orientation average: a copy queued on the caller's stream
+    right after each call sees the whole profile (the join), bitwise equal to
+    a call on the default stream.  The 20,000-atom globule with 200 q on
+    [0, 1] splits under the cost model; the other grids are fallbacks in case
+    a recalibration moves the split, and one of them must split."""
     import torch
 
     say("hybrid split on a side stream, joined into the caller's stream")
-    m = _globule(20000, W.q_grid(0.0, 1.0, 100), 13062258 + 60)
-    c, t, tab = to_dev(m)
-    ref, n_ref = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
-    print(f"averaged q values: {n_ref}")
+    for q1, nq in ((1.0, 200), (1.5, 200), (1.0, 100), (0.6, 100)):
+        m = _globule(20000, W.q_grid(0.0, q1, nq), 13062258 + 60)
+        c, t, tab = to_dev(m)
+        ref, n_ref = sd.debye_profile_hybrid(c, t, tab, m.q, tol=1e-10)
+        print(f"[0, {q1}] with {nq} q: averaged q values: {n_ref}")
+        if 0 < n_ref < len(m.q):
+            break
     assert 0 < n_ref < len(m.q)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -192,12 +197,14 @@ def test_hybrid_small_workspace(sd):
 
     say("hybrid with a reduced workspace")
     lib = _lib.load()
-    n = 6000
+    # (8,000 atoms: large enough that the automatic split averages the low q
+    # values with a full workspace, the averaged part carrying a fixed cost)
+    n = 8000
     rng = W.rng_for(13062258 + 61)
     pts = W.uniform_ball_min_sep(rng, n, W.globular_radius(n), 1.0)
     types = W.draw_types(rng, n)
     q = W.q_grid(0.0, 0.12, 40)
-    m = W.Molecule("globular_6k", np.ascontiguousarray(pts, dtype=np.float32), types,
+    m = W.Molecule("globular_8k", np.ascontiguousarray(pts, dtype=np.float32), types,
                    W.gaussian_table(W.TYPE_Z, W.TYPE_B, q), q)
     c, t, tab = to_dev(m)
     ctx = sd.Context(0)
