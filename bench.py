@@ -478,10 +478,11 @@ def bench_hybrid(sd, W, torch, dev):
 
 
 def bench_hybrid_split(sd, W, torch, dev, ctx):
-    """A 20,000-atom globule on 100 q in [0, 1], where the hybrid averages a
-    prefix and sums the rest directly on a second stream: the call against
-    the two parts run alone and against the direct sum of every q."""
-    m = W.globular(20000, nq=100)
+    """A 20,000-atom globule on 200 q in [0, 1], where the automatic hybrid
+    averages a low-q prefix and sums the rest directly on a second stream:
+    the call against the two parts run alone and against the direct sum of
+    every q."""
+    m = W.globular(20000, nq=200)
     coords = torch.from_numpy(m.coords).to(dev)
     types = torch.from_numpy(m.types).to(dev)
     table = torch.from_numpy(m.table).to(dev)
