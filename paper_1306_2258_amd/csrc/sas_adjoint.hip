@@ -568,7 +568,7 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
     for (int32_t ch = 0; ch < nchunks; ++ch) {
       const int64_t base = static_cast<int64_t>(ch) * a.n_strips;
       const int64_t first = row_first_strip(I, nJ, c, g);
-      const int64_t spr = ceil_div(nJ - I / c, g);
+      const int64_t spr = strips_in_row(I, nJ, c, g);
       for (int64_t s = first; s < first + spr; ++s) {
         const double* p = a.gI + ((base + s) * ib + lane) * 3;
         sx += p[0];
@@ -577,10 +577,8 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
       }
       const int64_t rows = min(nI, (J + 1) * c);
       for (int64_t Ip = 0; Ip < rows; ++Ip) {
-        const int64_t u = Ip / c;
-        const int64_t gi = (J - u) / g;
-        const int64_t s = row_first_strip(Ip, nJ, c, g) + gi;
-        const int64_t ja = u + gi * g;
+        int64_t ja = 0;
+        const int64_t s = strip_holding(Ip, J, nJ, c, g, &ja);
         const double* p = a.gJ + ((base + s) * g * bj + (at - ja * bj)) * 3;
         sx += p[0];
         sy += p[1];

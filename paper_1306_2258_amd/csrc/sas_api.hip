@@ -15,6 +15,7 @@
 
 #include "../../include/sas_debye.h"
 #include "sas_kernels.hpp"
+#include "sas_schedule.hpp"
 
 using sas::DescView;
 using sas::Geometry;

@@ -27,14 +27,6 @@
 
 namespace sas {
 
-int64_t strips_of(int64_t n, const Geometry& geo) {
-  if (n < 2) return 0;
-  const int64_t nI = ceil_div(n, geo.ib), nJ = ceil_div(n, geo.bj), c = geo.c, g = geo.g;
-  const int64_t nsup = ceil_div(nI, c);
-  const int64_t last_rows = nI - (nsup - 1) * c;
-  return strips_before(nsup - 1, nJ, c, g) + last_rows * ceil_div(nJ - (nsup - 1), g);
-}
-
 int64_t slices_of(int64_t n_strips) { return ceil_div(n_strips, kSliceTiles); }
 
 // ---------------------------------------------------------------------------

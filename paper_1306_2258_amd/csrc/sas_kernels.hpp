@@ -89,7 +89,6 @@ struct AdjArgs {
 };
 
 // Host-side helpers implemented in sas_kernels.hip / sas_adjoint.hip.
-int64_t strips_of(int64_t n, const Geometry& g);
 int64_t slices_of(int64_t n_strips);
 
 hipError_t launch_pack(const float* coords, const int32_t* types, const DescView& sd, int32_t S,

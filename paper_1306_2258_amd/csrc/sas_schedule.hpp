@@ -33,11 +33,35 @@ __host__ __device__ inline int64_t row_first_strip(int64_t I, int64_t nJ, int64_
   return strips_before(u, nJ, c, g) + (I - u * c) * ceil_div(nJ - u, g);
 }
 
+// Strips of row I (J blocks floor(I/c) .. nJ-1 in runs of g).
+__host__ __device__ inline int64_t strips_in_row(int64_t I, int64_t nJ, int64_t c, int64_t g) {
+  return ceil_div(nJ - I / c, g);
+}
+
+// The strip of row I that holds J block J (floor(I/c) <= J < nJ), and that
+// strip's first J block in *ja.
+__host__ __device__ inline int64_t strip_holding(int64_t I, int64_t J, int64_t nJ, int64_t c, int64_t g, int64_t* ja) {
+  const int64_t u = I / c;
+  const int64_t gi = (J - u) / g;
+  *ja = u + gi * g;
+  return row_first_strip(I, nJ, c, g) + gi;
+}
+
+// Strips of one structure of n atoms (none below two atoms).
+__host__ __device__ inline int64_t strips_of(int64_t n, const Geometry& geo) {
+  if (n < 2) return 0;
+  const int64_t nI = ceil_div(n, geo.ib), nJ = ceil_div(n, geo.bj), c = geo.c, g = geo.g;
+  const int64_t nsup = ceil_div(nI, c);
+  const int64_t last_rows = nI - (nsup - 1) * c;
+  return strips_before(nsup - 1, nJ, c, g) + last_rows * ceil_div(nJ - (nsup - 1), g);
+}
+
 struct StripPos {
   int32_t I, Ja, Jb;
 };
 
-__device__ inline StripPos decode_strip(int64_t t, int32_t n, const Geometry& geo) {
+// Row I, first J block Ja and end Jb of strip t (0 <= t < strips_of(n)).
+__host__ __device__ inline StripPos decode_strip(int64_t t, int32_t n, const Geometry& geo) {
   const int64_t nI = ceil_div(n, geo.ib), nJ = ceil_div(n, geo.bj), c = geo.c, g = geo.g;
   const int64_t nsup = ceil_div(nI, c);
   // largest u in [0, nsup) with strips_before(u) <= t

@@ -11,10 +11,16 @@ holds timings only), so the oracle is pinned by:
   * invariances: rotation, translation, permutation, type relabelling, the
     bitwise power-of-two scaling r -> 2r, q -> q/2, bounds 0 < I <= (sum|f|)^2,
     the large-q limit, per-type vs per-atom tables, atom duplication;
-  * the gradient against central finite differences of the profile and the
-    exact identities sum_i g_i = 0, sum_i x_i x g_i = 0.
-A mutation test compiles deliberately broken copies of the oracle source and
-checks that these pins reject every one of them.
+  * the second output A(q) = sum |f f sinc| (the cancellation measure
+    kappa = A / I): one and two atoms and the tetrahedron at products q r
+    where sin is known exactly, A = I where no term is negative,
+    |I| <= A <= (sum|f|)^2, A(0) = (sum|f(0)|)^2, and the mpmath brute force;
+  * the gradient against central finite differences of the profile (by norm
+    and element by element), a two-atom closed form and the exact identities
+    sum_i g_i = 0, sum_i x_i x g_i = 0.
+A mutation test compiles deliberately broken copies of the oracle source
+(mistakes in I, in A and in the gradient) and checks that these pins reject
+every one of them.
 """
 from __future__ import annotations
 
@@ -136,25 +142,35 @@ def pin_eq1(profile):
 
 
 def pin_mpmath(profile):
-    import mpmath
-
-    mpmath.mp.dps = 50
     m = W.random_molecule(11, 12, 5, q0=0.0, q1=1.5, extent=12.0)
     I = profile(m.coords, m.types, m.table, m.q)
+    exp, _ = mpmath_profile_abs(m)
+    assert rel(I, exp) < 1e-13
+
+
+def mpmath_profile_abs(m, dps=50):
+    """Eq. 2 and A(q) = sum |f f sinc| by brute force over all (i, j) at 50 digits."""
+    import mpmath
+
+    mpmath.mp.dps = dps
     c = [[mpmath.mpf(float(v)) for v in row] for row in m.coords]
-    exp = []
+    exp, exp_abs = [], []
     for k, qm in enumerate(m.q):
         qq = mpmath.mpf(float(qm))
         tot = mpmath.mpf(0)
+        tot_abs = mpmath.mpf(0)
         for i in range(m.n):
             fi = mpmath.mpf(float(m.table[m.types[i], k]))
             for j in range(m.n):
                 fj = mpmath.mpf(float(m.table[m.types[j], k]))
                 r = mpmath.sqrt(sum((c[i][d] - c[j][d]) ** 2 for d in range(3)))
                 x = qq * r
-                tot += fi * fj * (1 if x == 0 else mpmath.sin(x) / x)
+                term = fi * fj * (1 if x == 0 else mpmath.sin(x) / x)
+                tot += term
+                tot_abs += abs(term)
         exp.append(float(tot))
-    assert rel(I, exp) < 1e-13
+        exp_abs.append(float(tot_abs))
+    return np.array(exp), np.array(exp_abs)
 
 
 def pin_invariances(profile):
@@ -213,9 +229,96 @@ PINS = [pin_single_atom, pin_two_atoms, pin_q_zero, pin_polyhedra, pin_eq1, pin_
         pin_large_q, pin_type_factoring, pin_duplication]
 
 
+# ---------------------------------------------------------------------------
+# Pins of the second output A(q) = sum_k sum_j |f_k f_j sinc(q r_jk)| (the
+# cancellation measure kappa = A / I).  Each takes profile_abs(coords, types,
+# table, q) -> (I, A).  Closed forms use products q r at which sin is known
+# exactly (multiples of pi/2), so no expected value re-calls a sine.
+# ---------------------------------------------------------------------------
+
+def apin_single_atom(profile_abs):
+    # A = f^2, also for negative form factors (the diagonal's |f f|)
+    table = np.array([[-1.5, 2.0, -0.25, 0.75]])
+    q = np.array([0.0, 0.4, 1.3, 2.9])
+    _, A = profile_abs(np.array([[0.3, -1.0, 2.0]]), np.array([0]), table, q)
+    assert rel(A, table[0] ** 2) < 1e-15
+
+
+def apin_two_atoms(profile_abs):
+    # r = 2 exactly: q r = pi/2, 3pi/2, 5pi/2, 7pi/2, pi and 0, where sinc is
+    # 2/pi, -2/(3pi), 2/(5pi), -2/(7pi), 0 (to 1e-16) and 1; form-factor
+    # products of both signs
+    coords = np.array([[0.0, 0.0, 0.0], [0.0, 2.0, 0.0]])
+    q = np.array([0.0, math.pi / 4, math.pi / 2, 3 * math.pi / 4, 5 * math.pi / 4, 7 * math.pi / 4])
+    s = np.array([1.0, 2 / math.pi, 0.0, -2 / (3 * math.pi), 2 / (5 * math.pi), -2 / (7 * math.pi)])
+    table = np.array([[1.5, -2.0, 0.5, 3.0, -1.25, 0.8], [-3.0, 0.25, 4.0, 1.5, -2.0, 2.5]])
+    I, A = profile_abs(coords, np.array([0, 1]), table, q)
+    f1, f2 = table[0], table[1]
+    assert rel(A, f1 ** 2 + f2 ** 2 + 2 * np.abs(f1 * f2 * s)) < 1e-14
+    assert rel(I, f1 ** 2 + f2 ** 2 + 2 * f1 * f2 * s) < 1e-14
+
+
+def apin_tetrahedron(profile_abs):
+    # one type, edge a: A = 4 f^2 (1 + 3 |s(a)|); q a = 3pi/2 and 7pi/2 make s < 0
+    a = 3.7
+    q = np.array([0.0, 0.5 * math.pi / a, 1.5 * math.pi / a, 3.5 * math.pi / a])
+    s = np.array([1.0, 2 / math.pi, -2 / (3 * math.pi), -2 / (7 * math.pi)])
+    f = np.array([6.0, -5.5, 4.0, 2.5])
+    I, A = profile_abs(_tetrahedron(a), np.zeros(4, dtype=np.int32), f[None, :], q)
+    assert rel(A, 4 * f ** 2 * (1 + 3 * np.abs(s))) < 1e-13
+    assert rel(I, 4 * f ** 2 * (1 + 3 * s)) < 1e-13
+
+
+def apin_equals_profile_when_no_term_is_negative(profile_abs):
+    # positive form factors and q D < pi: every sinc > 0, so A = I
+    m = W.random_molecule(91, 40, 9, q0=0.0, q1=0.3, extent=8.0)
+    c = m.coords.astype(np.float64)
+    d = np.sqrt(((c[:, None] - c[None]) ** 2).sum(-1)).max()
+    assert m.q[-1] * d < math.pi and np.all(m.table > 0)
+    I, A = profile_abs(m.coords, m.types, m.table, m.q)
+    assert rel(A, I) < 1e-14
+
+
+def apin_bounds_and_q_zero(profile_abs):
+    # |I| <= A <= (sum |f|)^2 everywhere, A(0) = (sum |f(0)|)^2, and A > I
+    # where terms cancel (form factors of both signs, q D up to ~60)
+    m = W.random_molecule(93, 50, 12, t=3, q0=0.0, q1=3.0, extent=20.0)
+    table = m.table.astype(np.float64) * np.array([1.0, -1.0, 0.5])[:, None]
+    I, A = profile_abs(m.coords, m.types, table, m.q)
+    fabs = np.abs(table)[m.types].sum(axis=0)
+    assert np.all(np.abs(I) <= A * (1 + 1e-14))
+    assert np.all(A <= fabs ** 2 * (1 + 1e-14))
+    assert rel(A[0], fabs[0] ** 2) < 1e-14
+    assert np.all(A[1:] > np.abs(I[1:]) * (1 + 1e-3))
+
+
+def apin_mpmath(profile_abs):
+    m = W.random_molecule(13, 10, 4, q0=0.0, q1=2.5, extent=10.0)
+    table = m.table.astype(np.float64)
+    table[1] *= -1.0
+    m.table = table
+    I, A = profile_abs(m.coords, m.types, table, m.q)
+    exp_I, exp_A = mpmath_profile_abs(m)
+    assert rel(I, exp_I) < 1e-13
+    assert rel(A, exp_A) < 1e-13
+
+
+APINS = [apin_single_atom, apin_two_atoms, apin_tetrahedron, apin_equals_profile_when_no_term_is_negative,
+         apin_bounds_and_q_zero, apin_mpmath]
+
+
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
 def test_oracle_profile_pin(pin):
     pin(oracle.profile)
+
+
+def _oracle_profile_abs(coords, types, table, q):
+    return oracle.profile(coords, types, table, q, with_abs=True)
+
+
+@pytest.mark.parametrize("pin", APINS, ids=[p.__name__ for p in APINS])
+def test_oracle_abs_pin(pin):
+    pin(_oracle_profile_abs)
 
 
 def test_numpy_transcription_matches_c_oracle():
@@ -242,9 +345,15 @@ def _grad_case():
     return m.coords.astype(np.float64), m.types, m.table.astype(np.float64), m.q, w
 
 
-def test_grad_vs_central_differences():
+# Each gradient pin takes grad(coords, types, table, q, w, atoms=None) and the
+# (pinned) profile oracle, so that the mutation test can run them on broken
+# gradient oracles too.
+
+def gpin_central_differences(grad, profile):
+    """Every coordinate of a small two-type molecule against central
+    differences of the pinned profile oracle (h = 1e-5 A)."""
     c, t, tab, q, w = _grad_case()
-    g = oracle.grad(c, t, tab, q, w)
+    g = grad(c, t, tab, q, w)
     h = 1e-5
     num = np.zeros_like(c)
     for i in range(c.shape[0]):
@@ -253,17 +362,56 @@ def test_grad_vs_central_differences():
             cm = c.copy()
             cp[i, d] += h
             cm[i, d] -= h
-            num[i, d] = (w @ oracle.profile(cp, t, tab, q) - w @ oracle.profile(cm, t, tab, q)) / (2 * h)
+            num[i, d] = (w @ profile(cp, t, tab, q) - w @ profile(cm, t, tab, q)) / (2 * h)
     assert np.linalg.norm(g - num) / np.linalg.norm(num) < 1e-7
+    # element by element as well: no atom hides under the norm
+    assert np.max(np.abs(g - num)) < 1e-6 * np.max(np.abs(num))
 
 
-def test_grad_identities():
+def gpin_identities(grad, profile):
+    """Translation and rotation invariance of Eq. 2: the forces and their
+    torques sum to zero."""
     c, t, tab, q, w = _grad_case()
-    g = oracle.grad(c, t, tab, q, w)
+    g = grad(c, t, tab, q, w)
     scale = np.abs(g).sum()
     assert np.abs(g.sum(axis=0)).max() < 1e-12 * scale
     torque = np.cross(c, g).sum(axis=0)
     assert np.abs(torque).max() < 1e-12 * scale * np.abs(c).max()
+
+
+def gpin_q_zero_and_coincident_atoms_are_zero(grad, profile):
+    """I(0) does not depend on the positions, and the derivative of sinc
+    vanishes at 0: q = 0 weights and coincident atoms give no force."""
+    c = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 2.0, 0.5]])
+    tab = np.array([[2.0, 1.0]])
+    q = np.array([0.0, 0.7])
+    g = grad(c, np.zeros(3, dtype=np.int32), tab, q, np.array([1.0, 0.0]))
+    assert np.all(g == 0.0)
+    g2 = grad(c[:2], np.zeros(2, dtype=np.int32), tab, q, np.array([0.0, 1.0]))
+    assert np.all(g2 == 0.0)
+
+
+def gpin_two_atoms_closed_form(grad, profile):
+    """Two atoms along x at r = 2 with q r = pi/2 (sin = 1, cos = 0): the
+    derivative of 2 f1 f2 sin(q r)/(q r) along the axis is
+    2 f1 f2 (cos(q r)/r - sin(q r)/(q r^2)) = -2 f1 f2 / (q r^2)."""
+    c = np.array([[0.0, 0.0, 0.0], [2.0, 0.0, 0.0]])
+    q = np.array([math.pi / 4])
+    tab = np.array([[1.5], [-2.5]])
+    g = grad(c, np.array([0, 1]), tab, q, np.array([1.0]))
+    d = -2.0 * 1.5 * -2.5 / (q[0] * 4.0)  # dI/dr
+    # atom 1 moves away from atom 0 along +x: dI/dx_1 = dI/dr, dI/dx_0 = -dI/dr
+    assert rel(g[:, 0], np.array([-d, d])) < 1e-14
+    assert np.all(g[:, 1:] == 0.0)
+
+
+GPINS = [gpin_central_differences, gpin_identities, gpin_q_zero_and_coincident_atoms_are_zero,
+         gpin_two_atoms_closed_form]
+
+
+@pytest.mark.parametrize("pin", GPINS, ids=[p.__name__ for p in GPINS])
+def test_oracle_grad_pin(pin):
+    pin(oracle.grad, oracle.profile)
 
 
 def test_grad_atom_subset_matches_full():
@@ -271,14 +419,6 @@ def test_grad_atom_subset_matches_full():
     g = oracle.grad(c, t, tab, q, w)
     sub = np.array([3, 0, 17, 9])
     assert np.array_equal(oracle.grad(c, t, tab, q, w, atoms=sub), g[sub])
-
-
-def test_grad_q_zero_and_coincident_atoms_are_zero():
-    c = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.0, 2.0, 0.5]])
-    tab = np.array([[2.0, 1.0]])
-    q = np.array([0.0, 0.7])
-    g = oracle.grad(c, np.zeros(3, dtype=np.int32), tab, q, np.array([1.0, 0.0]))
-    assert np.all(g == 0.0)
 
 
 def test_chi2_weights_are_the_derivative():
@@ -346,6 +486,8 @@ def test_grad_table_euler_identity_and_special_cases():
 # (on the CPU) must each be caught by at least one pin.
 # ---------------------------------------------------------------------------
 
+# Mistakes in the profile I(q) (caught by PINS), in A(q) (caught by APINS)
+# and in the gradient (caught by GPINS).
 MUTANTS = {
     "no_doubling": ("double term = 2.0 * fk[m]", "double term = 1.0 * fk[m]"),
     "no_diagonal": ("neu_add(&tot, f * f);", "(void)0;"),
@@ -356,6 +498,23 @@ MUTANTS = {
     "dropped_dz": ("sqrt(dx * dx + dy * dy + dz * dz);\n        const double* fj",
                    "sqrt(dx * dx + dy * dy);\n        const double* fj"),
     "transposed_table": ("double f = table[(int64_t)types[k] * nq + m];", "double f = table[(int64_t)m * t + types[k] % t];"),
+}
+ABS_MUTANTS = {
+    "abs_dropped": ("neu_add(&sA[m], fabs(term));", "neu_add(&sA[m], term);"),
+    "abs_no_diagonal": ("neu_add(&tabs, f * f);", "(void)0;"),
+    "abs_of_sinc_only": ("neu_add(&sA[m], fabs(term));", "neu_add(&sA[m], 2.0 * fk[m] * fj[m] * fabs(sinc(q[m] * r)));"),
+    "abs_not_doubled": ("neu_add(&sA[m], fabs(term));", "neu_add(&sA[m], 0.5 * fabs(term));"),
+}
+GRAD_MUTANTS = {
+    "grad_no_sine_term": ("double dsinc_dr = cos(x) / r - sin(x) / (q[m] * r * r);", "double dsinc_dr = cos(x) / r;"),
+    "grad_sign": ("double dsinc_dr = cos(x) / r - sin(x) / (q[m] * r * r);",
+                  "double dsinc_dr = sin(x) / (q[m] * r * r) - cos(x) / r;"),
+    "grad_no_factor_two": ("neu_add(&dsum, 2.0 * w[m]", "neu_add(&dsum, 1.0 * w[m]"),
+    "grad_partner_type": ("const double* fj = table + (int64_t)types[j] * nq;\n      neu_t dsum",
+                          "const double* fj = table + (int64_t)types[i] * nq;\n      neu_t dsum"),
+    "grad_not_unit_direction": ("double g = neu_val(&dsum) / r;", "double g = neu_val(&dsum);"),
+    "grad_q_zero_kept": ("if (q[m] == 0.0) continue;", "(void)0;"),
+    "grad_dropped_dz": ("neu_add(&gz, g * dz);", "neu_add(&gz, g * dy);"),
 }
 
 
@@ -369,31 +528,69 @@ def _build_mutant(tmp_path, name, old, new):
     lib = ctypes.CDLL(str(so))
     P = ctypes.c_void_p
     lib.oracle_debye_profile.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int32, P, P, ctypes.c_int]
+    lib.oracle_debye_grad.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int32, P, P,
+                                      ctypes.c_int64, P, ctypes.c_int]
 
-    def profile(coords, types, table, q):
-        c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(-1, 3))
-        t = np.ascontiguousarray(np.asarray(types, dtype=np.int32))
-        tab = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
-        qq = np.ascontiguousarray(np.asarray(q, dtype=np.float64))
+    def arrays(coords, types, table, q):
+        return (np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(-1, 3)),
+                np.ascontiguousarray(np.asarray(types, dtype=np.int32)),
+                np.ascontiguousarray(np.asarray(table, dtype=np.float64)),
+                np.ascontiguousarray(np.asarray(q, dtype=np.float64)))
+
+    def profile_abs(coords, types, table, q):
+        c, t, tab, qq = arrays(coords, types, table, q)
         out = np.zeros(len(qq))
         a = np.zeros(len(qq))
         lib.oracle_debye_profile(c.ctypes.data, t.ctypes.data, c.shape[0], tab.ctypes.data, tab.shape[0],
                                  qq.ctypes.data, len(qq), out.ctypes.data, a.ctypes.data, 1)
-        return out
+        return out, a
 
-    return profile
+    def profile(coords, types, table, q):
+        return profile_abs(coords, types, table, q)[0]
+
+    def grad(coords, types, table, q, w, atoms=None):
+        c, t, tab, qq = arrays(coords, types, table, q)
+        ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        assert atoms is None
+        g = np.zeros((c.shape[0], 3))
+        lib.oracle_debye_grad(c.ctypes.data, t.ctypes.data, c.shape[0], tab.ctypes.data, tab.shape[0],
+                              qq.ctypes.data, len(qq), ww.ctypes.data, None, c.shape[0], g.ctypes.data, 1)
+        return g
+
+    return profile, profile_abs, grad
+
+
+def _caught(checks):
+    caught = []
+    for name, fn in checks:
+        try:
+            fn()
+        except AssertionError:
+            caught.append(name)
+    return caught
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_reject_mutant(tmp_path, name):
     old, new = MUTANTS[name]
-    profile = _build_mutant(tmp_path, name, old, new)
-    caught = []
-    for pin in PINS:
-        if pin is pin_mpmath:
-            continue  # slow, and redundant for structural mistakes
-        try:
-            pin(profile)
-        except AssertionError:
-            caught.append(pin.__name__)
-    assert caught, f"no pin caught mutant {name}"
+    profile, _, _ = _build_mutant(tmp_path, name, old, new)
+    checks = [(pin.__name__, lambda pin=pin: pin(profile)) for pin in PINS if pin is not pin_mpmath]
+    assert _caught(checks), f"no pin caught mutant {name}"  # (mpmath: slow, redundant for these)
+
+
+@pytest.mark.parametrize("name", sorted(ABS_MUTANTS))
+def test_abs_pins_reject_mutant(tmp_path, name):
+    old, new = ABS_MUTANTS[name]
+    profile, profile_abs, _ = _build_mutant(tmp_path, name, old, new)
+    checks = [(pin.__name__, lambda pin=pin: pin(profile_abs)) for pin in APINS if pin is not apin_mpmath]
+    assert _caught(checks), f"no A(q) pin caught mutant {name}"
+    # the mistakes are in A only: the profile pins still pass
+    assert not _caught([(pin.__name__, lambda pin=pin: pin(profile)) for pin in PINS if pin is not pin_mpmath])
+
+
+@pytest.mark.parametrize("name", sorted(GRAD_MUTANTS))
+def test_grad_pins_reject_mutant(tmp_path, name):
+    old, new = GRAD_MUTANTS[name]
+    _, _, grad = _build_mutant(tmp_path, name, old, new)
+    checks = [(pin.__name__, lambda pin=pin: pin(grad, oracle.profile)) for pin in GPINS]
+    assert _caught(checks), f"no gradient pin caught mutant {name}"
