@@ -358,3 +358,46 @@ def test_plan_reuses_tuned_shape(sd):
     assert torch.equal(a, b)
     p1.close()
     p2.close()
+
+
+def test_full_ensemble_plan_against_oracle(sd):
+    """The batching workload at full size: 256 globular structures of 500 to
+    8,000 atoms on 100 q over [0, 0.8], as one plan (tuned tile shape,
+    largest-first order, captured graph) replayed twice with eager work in
+    between.  Eight members (the largest, the smallest and six drawn with a
+    fixed seed) against their stored oracle profiles at every q; all 256
+    bitwise against plain calls with the plan's tile shape."""
+    import torch
+
+    from tests.golden.make_golden import ensemble_members, load_ensemble
+
+    say("full ensemble: 256 structures, plan replay vs stored oracle members and plain calls")
+    e = W.globular_ensemble()
+    gold = load_ensemble()
+    assert sorted(gold) == sorted(ensemble_members(e.sizes))
+    c = torch.from_numpy(e.coords).cuda()
+    t = torch.from_numpy(e.types).cuda()
+    tab = torch.from_numpy(e.table).cuda()
+    ctx = sd.Context(0)
+    plan = sd.BatchedPlan(c, t, e.offsets, tab, e.q, ctx=ctx)
+    first = plan.execute().clone()
+    bj, qc = ctx.variant()
+    ctx2 = sd.Context(0)
+    ctx2.set_variant(bj, qc)
+    eager = sd.debye_profile_batched(c, t, e.offsets, tab, e.q, ctx=ctx2)
+    second = plan.execute().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(first, second) and torch.equal(first, eager)
+    got = second.cpu().numpy()
+    worst = 0.0
+    for s, (q, I, _) in gold.items():
+        assert np.array_equal(q, e.q)
+        err = rel_err(got[s], I)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= TOL, f"structure {s} (N={int(e.sizes[s])}): max rel err {err.max():.3e}"
+    print(f"tile shape bj={bj} qc={qc}; stored members: max rel err {worst:.3e}")
+    for s in range(len(e.sizes)):
+        a, b = int(e.offsets[s]), int(e.offsets[s + 1])
+        plain = sd.debye_profile(c[a:b], t[a:b], tab, e.q, ctx=ctx2)
+        assert torch.equal(second[s], plain), f"structure {s}"
+    plan.close()

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import workloads as W
+from tests.gradcheck import GTOL, assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -211,9 +212,6 @@ def test_nonuniform_batched_and_plan(sd):
     plan.close()
 
 
-GTOL = 1e-5
-
-
 def _grad_check(sd, m, w, atoms=None, with_profile=False):
     import torch
 
@@ -221,12 +219,9 @@ def _grad_check(sd, m, w, atoms=None, with_profile=False):
     wd = torch.from_numpy(np.asarray(w, dtype=np.float64)).cuda()
     out = sd.debye_grad(c, t, tab, m.q, wd, with_profile=with_profile)
     g = (out[0] if with_profile else out).cpu().numpy()
-    assert np.all(np.isfinite(g))
     ref = oracle.grad(m.coords, m.types, m.table, m.q, w, atoms=atoms)
     got = g if atoms is None else g[atoms]
-    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    print(f"grad rel err {e:.3e}")
-    assert e <= GTOL, e
+    assert_grad_close(got, ref, GTOL, f"direct N={m.n} Nq={len(m.q)}")
     return out
 
 
@@ -270,7 +265,7 @@ def test_nonuniform_autograd(sd):
     (I * torch.from_numpy(w).cuda()).sum().backward()
     ref = oracle.grad(m.coords, m.types, m.table, m.q, w)
     got = x.grad.double().cpu().numpy()
-    assert float(np.linalg.norm(got - ref) / np.linalg.norm(ref)) <= GTOL
+    assert_grad_close(got, ref, GTOL, "autograd, log grid")
 
 
 def test_dna_rod_50k_log_grid(sd):
@@ -284,3 +279,32 @@ def test_dna_rod_50k_log_grid(sd):
     err = rel_err(got[pick], ref)
     print("sampled q errors", " ".join(f"{e:.2e}" for e in err))
     assert err.max() <= TOL
+
+
+def test_forced_direct_form_applies_to_both_gradients(sd):
+    """With the context's form set to 'direct', both gradient calls take the
+    direct variants on a uniform grid: the profile each returns equals the
+    forced direct plain profile bitwise (and differs from the recurrence's),
+    and the gradients match the oracle."""
+    import torch
+
+    say("forced direct form: coordinate and table gradients on a uniform grid")
+    m = W.random_molecule(797, 600, 50, t=3, q0=0.0, q1=0.9, extent=24.0)
+    c, t, tab = to_dev(m)
+    w = np.random.default_rng(17).normal(size=len(m.q))
+    wd = torch.from_numpy(w).cuda()
+    ctx = sd.Context(0)
+    ctx.set_form("direct")
+    plain = sd.debye_profile(c, t, tab, m.q, ctx=ctx).cpu().numpy()
+    assert ctx.form() == "direct"
+    recurrence = gpu_profile(sd, m)
+    assert not np.array_equal(plain, recurrence)
+    g, I = sd.debye_grad(c, t, tab, m.q, wd, with_profile=True, ctx=ctx)
+    assert np.array_equal(I.cpu().numpy(), plain)
+    assert_grad_close(g.cpu().numpy(), oracle.grad(m.coords, m.types, m.table, m.q, w), GTOL, "forced direct")
+    gt, I2 = sd.debye_grad_table(c, t, tab, m.q, wd, with_profile=True, ctx=ctx)
+    assert np.array_equal(I2.cpu().numpy(), plain)
+    ref_t = oracle.grad_table(m.coords, m.types, m.table, m.q, w)
+    got_t = gt.cpu().numpy()
+    err = np.linalg.norm(got_t - ref_t, axis=1) / np.linalg.norm(ref_t, axis=1)
+    assert err.max() <= GTOL, err

@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 import workloads as W
+from tests.gradcheck import assert_grad_close
 
 pytestmark = pytest.mark.gpu
 
@@ -146,7 +147,7 @@ def test_table_grad_autograd(sd):
     gt = f.grad.double().cpu().numpy()
     assert np.linalg.norm(gt - ref_t) / np.linalg.norm(ref_t) <= GTOL
     gc = x.grad.double().cpu().numpy()
-    assert np.linalg.norm(gc - ref_c) / np.linalg.norm(ref_c) <= GTOL
+    assert_grad_close(gc, ref_c, GTOL, "autograd with the table")
 
 
 def test_table_grad_globular_10k_sampled(sd):
