@@ -25,7 +25,16 @@
  *    memory.  It owns only sas_ctx and sas_plan objects.
  *  - Device work is enqueued asynchronously on `stream` (a hipStream_t passed
  *    as void*; NULL is the default stream).  Results are valid once the
- *    stream reaches the call.  No call synchronises the stream.
+ *    stream reaches the call.  No call synchronises the stream, except the
+ *    hybrid profile and the debug mode (both below).  Host-written blocks
+ *    that a call needs on the device (a batched call's descriptors, a
+ *    non-uniform q grid) go through a ring of pinned staging buffers owned by
+ *    the context; the host waits only if every slot's copy is still queued.
+ *  - Graph capture: calls on a single structure with a uniform q grid upload
+ *    nothing and may be captured into a caller's graph.  A call that would
+ *    upload a host block, the hybrid profile and the debug mode refuse a
+ *    capturing stream with SAS_ERR_UNSUPPORTED before enqueueing anything;
+ *    a batched plan (sas_plan_*) is the capturable form of the batched call.
  *  - Scratch memory is the caller's `workspace` (dev, 256-byte aligned) of at
  *    least the size the matching *_workspace_size query returns.
  *  - The q grid is host double [nq], finite, q_0 >= 0 and strictly
@@ -274,8 +283,9 @@ sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
  * SAS_FORM_PER_ATOM weights every pair term by f_j inside the q loop even
  * for few types.  sas_get_form reports the form the last profile call used:
  * SAS_FORM_RECURRENCE or SAS_FORM_DIRECT, plus SAS_FORM_PER_ATOM when set.
- * The gradient uses the type-sorted form, and the direct variant exactly
- * when the grid is not uniform.
+ * Both gradients (sas_debye_grad, sas_debye_grad_table) follow the same
+ * flags: the direct variants on non-uniform grids or with SAS_FORM_DIRECT,
+ * the per-atom variants with many table rows or SAS_FORM_PER_ATOM.
  * Errors: SAS_ERR_INVALID_ARG (NULL, unknown flags).
  */
 #define SAS_FORM_AUTO 0

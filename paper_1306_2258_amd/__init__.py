@@ -82,9 +82,15 @@ class Context:
         return self._h
 
     def workspace(self, nbytes: int) -> torch.Tensor:
-        """A device byte buffer of at least nbytes, reused across calls on this context."""
+        """A device byte buffer of at least nbytes, reused across calls on this
+        context.  It is not regrown while the current stream is being
+        captured into a graph: a captured call would keep writing into the
+        buffer the growth releases."""
         nbytes = max(int(nbytes), 256)
         if self._ws is None or self._ws.numel() < nbytes:
+            if torch.cuda.is_current_stream_capturing():
+                raise RuntimeError(f"the context's workspace must grow to {nbytes} bytes during graph capture: "
+                                   "make one call of this size before capturing")
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._ws
 
@@ -342,7 +348,8 @@ class DebyeProfile(torch.autograd.Function):
     """I(q) = DebyeProfile.apply(coords, types, table, q): differentiable with
     respect to ``coords`` (float32 [N, 3]) through the library's adjoint
     kernel (sas_debye_grad) and with respect to ``table`` (float32 [T, Nq],
-    T <= 64) through sas_debye_grad_table."""
+    any number of rows: per-type sums up to 64 rows, per-atom sums beyond)
+    through sas_debye_grad_table."""
 
     @staticmethod
     def forward(ctx_, coords, types, table, q):

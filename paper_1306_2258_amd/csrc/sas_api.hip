@@ -57,11 +57,17 @@ struct sas_ctx {
   bool force_per_atom = false;  // per-atom form factors whatever T
   bool last_direct = false, last_per_atom = false;
   int32_t last_bj = 0, last_qc = 0;
-  // pinned staging for the batched call's descriptor upload
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t pinned_ev = nullptr;
-  bool pinned_used = false;
+  // pinned staging for the host-written blocks (descriptors of a batched
+  // call, a non-uniform q grid, the orientation rule): a ring of slots, each
+  // reused once the upload from it has completed
+  static constexpr int kStageSlots = 4;
+  struct Stage {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+  } stage[kStageSlots];
+  int stage_next = 0;
   std::mutex mu;
   // tile shape (bj, qc) chosen by timing, per workload key; filled by plans
   std::map<std::string, std::pair<int32_t, int32_t>> tuned;
@@ -430,9 +436,13 @@ DescView view_of(const Schedule& sc, const void* ws, const Layout& L) {
 // then a synchronisation of the stream.  Without it an out-of-range type is
 // clamped to the nearest valid row and non-finite coordinates give
 // non-finite results.
+sas_status refuse_capture(hipStream_t hs, const char* what);
+
 sas_status debug_validate(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n, int32_t t,
                           hipStream_t hs) {
   if (!ctx->debug_validate || n <= 0) return SAS_OK;
+  const sas_status cs = refuse_capture(hs, "debug mode (SAS_DEBUG_VALIDATE)");
+  if (cs != SAS_OK) return cs;
   if (!ctx->dbg) SAS_HIP(hipMalloc(reinterpret_cast<void**>(&ctx->dbg), 4 * sizeof(unsigned long long)));
   SAS_HIP(hipMemsetAsync(ctx->dbg, 0, 2 * sizeof(unsigned long long), hs));
   SAS_HIP(hipMemsetAsync(ctx->dbg + 2, 0xff, 2 * sizeof(unsigned long long), hs));
@@ -474,25 +484,48 @@ std::vector<char> upload_image(const Schedule& sc, const Layout& L, const QGrid&
   return img;
 }
 
-// Asynchronous upload through the context's pinned staging buffer.  The
-// buffer is reused once the previous upload from it has completed.
+// Calls whose host-written block (descriptors, a non-uniform q grid) goes
+// through the context's staging ring cannot be captured into a graph: the
+// captured copy would keep reading a slot that later calls overwrite.  A plan
+// (sas_plan_create_batched) is the capturable form of those calls.
+sas_status refuse_capture(hipStream_t hs, const char* what) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  SAS_HIP(hipStreamIsCapturing(hs, &cs));
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(SAS_ERR_UNSUPPORTED, "%s uploads host data through reused staging and cannot be captured; "
+                "use a batched plan (or a uniform q grid for single structures)", what);
+  return SAS_OK;
+}
+
+// Asynchronous upload through the next slot of the context's pinned staging
+// ring.  The host waits only when that slot's previous upload is still in
+// flight (kStageSlots uploads queued and unfinished).
 sas_status stage_upload_to(sas_ctx* ctx, void* dst, const std::vector<char>& img, hipStream_t hs) {
   if (img.empty()) return SAS_OK;
+  const sas_status cs = refuse_capture(hs, "this call");
+  if (cs != SAS_OK) return cs;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  if (ctx->pinned_used) SAS_HIP(hipEventSynchronize(ctx->pinned_ev));
-  if (ctx->pinned_bytes < img.size()) {
-    if (ctx->pinned) SAS_HIP(hipHostFree(ctx->pinned));
-    ctx->pinned = nullptr;
-    ctx->pinned_bytes = 0;
-    if (hipHostMalloc(&ctx->pinned, img.size(), hipHostMallocDefault) != hipSuccess)
-      return fail(SAS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes failed", img.size());
-    ctx->pinned_bytes = img.size();
+  sas_ctx::Stage& sl = ctx->stage[ctx->stage_next];
+  ctx->stage_next = (ctx->stage_next + 1) % sas_ctx::kStageSlots;
+  if (sl.used) {
+    hipError_t e = hipEventQuery(sl.ev);
+    if (e == hipErrorNotReady) e = hipEventSynchronize(sl.ev);
+    if (e != hipSuccess) return fail(SAS_ERR_HIP, "staging event: %s", hipGetErrorString(e));
   }
-  if (!ctx->pinned_ev) SAS_HIP(hipEventCreateWithFlags(&ctx->pinned_ev, hipEventDisableTiming));
-  std::memcpy(ctx->pinned, img.data(), img.size());
-  SAS_HIP(hipMemcpyAsync(dst, ctx->pinned, img.size(), hipMemcpyHostToDevice, hs));
-  SAS_HIP(hipEventRecord(ctx->pinned_ev, hs));
-  ctx->pinned_used = true;
+  if (sl.bytes < img.size()) {
+    if (sl.buf) SAS_HIP(hipHostFree(sl.buf));
+    sl.buf = nullptr;
+    sl.bytes = 0;
+    const size_t want = std::max<size_t>(img.size(), 4096);
+    if (hipHostMalloc(&sl.buf, want, hipHostMallocDefault) != hipSuccess)
+      return fail(SAS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes failed", want);
+    sl.bytes = want;
+  }
+  if (!sl.ev) SAS_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  std::memcpy(sl.buf, img.data(), img.size());
+  SAS_HIP(hipMemcpyAsync(dst, sl.buf, img.size(), hipMemcpyHostToDevice, hs));
+  SAS_HIP(hipEventRecord(sl.ev, hs));
+  sl.used = true;
   return SAS_OK;
 }
 
@@ -741,11 +774,13 @@ void sas_destroy(sas_ctx* ctx) {
         ctx->ev_pool.push_back(p.second);
       }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-    if (ctx->pinned_ev) {
-      (void)hipEventSynchronize(ctx->pinned_ev);
-      (void)hipEventDestroy(ctx->pinned_ev);
+    for (auto& sl : ctx->stage) {
+      if (sl.ev) {
+        (void)hipEventSynchronize(sl.ev);
+        (void)hipEventDestroy(sl.ev);
+      }
+      if (sl.buf) (void)hipHostFree(sl.buf);
     }
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->dbg) (void)hipFree(ctx->dbg);
     if (ctx->side) {
       (void)hipStreamSynchronize(ctx->side);
@@ -1166,7 +1201,8 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
     return enqueue_table_grad_by_atom(ctx, R, coords, types, n, table, t, nq, grid, dL_dI, grad_table_out, I_out,
                                       workspace, hs);
   }
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform, false, t);
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct,
+                                    false, t);
   const Layout L = make_layout(sc, t, nq);
   if (!workspace) return fail(SAS_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return fail(SAS_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -1203,10 +1239,11 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
   st = classify_q(q, nq, &grid);
   if (st != SAS_OK) return st;
   const double q0 = grid.q0, dq = grid.dq;
-  // a non-uniform grid takes the direct variants of the forward and the
-  // adjoint; many table rows (or a forced per-atom form) the per-atom ones
+  // a non-uniform grid (or a forced direct form) takes the direct variants
+  // of the forward and the adjoint; many table rows (or a forced per-atom
+  // form) the per-atom ones
   const bool pa = use_per_atom(ctx, t, n);
-  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform, pa);
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct, pa);
   if (pa)
     add_adjoint_pa(&sc, n, nq);
   else
@@ -1533,6 +1570,8 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
   hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = refuse_capture(hs, "the hybrid profile (it reads the radius back)");
+  if (st != SAS_OK) return st;
   st = debug_validate(ctx, coords, types, n, t, hs);
   if (st != SAS_OK) return st;
   char* w = static_cast<char*>(workspace);

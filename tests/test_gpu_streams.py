@@ -96,3 +96,50 @@ def test_plain_call_captured_in_caller_graph(sd):
     ref = oracle.profile(host, m.types, m.table, m.q)
     assert np.max(np.abs(out.cpu().numpy() - ref) / ref) <= 1e-6
     assert not torch.equal(out, eager)
+
+
+def test_capture_refused_for_calls_that_upload(sd):
+    """Calls that stage a host block (a batched call's descriptors, a
+    non-uniform q grid) would leave the captured copy reading a reused
+    staging slot; on a capturing stream they return SAS_ERR_UNSUPPORTED
+    before enqueueing anything, and the capture itself ends cleanly."""
+    import torch
+
+    say("capture refused: batched call, non-uniform grid, hybrid")
+    m = W.random_molecule(1620, 500, 30, q0=0.0, q1=0.8, extent=20.0)
+    ml = W.random_molecule(1621, 500, 0, q=W.log_grid(1e-3, 0.8, 30), extent=20.0)
+    c, t, tab = to_dev(m)
+    tabl = torch.from_numpy(ml.table).cuda()
+    off = np.array([0, 200, 500], dtype=np.int64)
+    ctx = sd.Context(0)
+    # warm the context's workspace to the largest size the calls below need
+    sd.debye_profile_batched(c, t, off, tab, m.q, ctx=ctx)
+    sd.debye_profile(c, t, tabl, ml.q, ctx=ctx)
+    sd.debye_profile_hybrid(c, t, tab, m.q, ctx=ctx)
+    torch.cuda.synchronize()
+    x = torch.zeros(4, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    statuses = []
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for call in (lambda: sd.debye_profile_batched(c, t, off, tab, m.q, ctx=ctx),
+                         lambda: sd.debye_profile(c, t, tabl, ml.q, ctx=ctx),
+                         lambda: sd.debye_profile_hybrid(c, t, tab, m.q, ctx=ctx)):
+                try:
+                    call()
+                    statuses.append(0)
+                except sd.SasError as e:
+                    statuses.append(e.status)
+            x.add_(1.0)
+    torch.cuda.synchronize()
+    assert statuses == [3, 3, 3], statuses
+    g.replay()
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.all(x == 2.0)
+    # the same calls still work eagerly afterwards
+    out = sd.debye_profile_batched(c, t, off, tab, m.q, ctx=ctx).cpu().numpy()
+    ref = oracle.profile(m.coords[200:], m.types[200:], m.table, m.q)
+    assert np.max(np.abs(out[1] - ref) / ref) <= 1e-6
