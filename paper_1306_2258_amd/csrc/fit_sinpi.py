@@ -1,13 +1,13 @@
 """Derives the FP32 coefficients of the direct form's sine and cosine polynomials.
 
 On |x| <= 1/2, with y = x^2:
-  sin(pi x) = x * P(y),            P of degree 4;
-  cos(pi x) = (1/4 - y) * R(y),    R of degree 4 (the factor holds the zeros
-                                   of the cosine at x = +-1/2, so R is smooth
-                                   and relative accuracy holds up to them);
-both minimising the largest relative error, by the Remez exchange on y in
-[0, 1/4]; the coefficients are then rounded to FP32.  Run it to reproduce
-kSinPi0..kSinPi4 and kCosR0..kCosR4 in sas_device.hpp:
+  sin(pi x) = x * P(y), P of degree 4, minimising the largest relative error;
+  cos(pi x) = Q(y),     Q of degree 5, minimising the largest absolute error
+                        (cos(pi x) vanishes at the ends, where only the
+                        absolute error matters for the sums it enters).
+Both by the Remez exchange on y in [0, 1/4]; the coefficients are then rounded
+to FP32.  Run it to reproduce kSinPi0..kSinPi4 and kCosPi0..kCosPi5 in
+sas_device.hpp:
 
     python paper_1306_2258_amd/csrc/fit_sinpi.py
 """
@@ -26,11 +26,7 @@ def sin_target(y: np.ndarray) -> np.ndarray:
 
 
 def cos_target(y: np.ndarray) -> np.ndarray:
-    """cos(pi sqrt(y)) / (1/4 - y), with its limit pi at y = 1/4."""
-    y = np.asarray(y, dtype=np.float64)
-    e = 0.25 - y
-    safe = np.where(e > 0, e, 1.0)
-    return np.where(e > 0, np.cos(np.pi * np.sqrt(y)) / safe, np.pi)
+    return np.cos(np.pi * np.sqrt(y))
 
 
 def remez(target=sin_target, deg: int = 4, relative: bool = True, iters: int = 40) -> tuple[np.ndarray, float]:
@@ -75,15 +71,12 @@ def main() -> None:
     print(f"sin: minimax relative error {level:.3e}; with FP32 coefficients {rel.max():.3e}")
     for k, c in enumerate(c32):
         print(f"kSinPi{k} = {float(c).hex()}f  // {float(c)!r}")
-    coef, level = remez(cos_target, 4, True)
+    coef, level = remez(cos_target, 5, False)
     c32 = coef.astype(np.float32)
-    approx = (0.25 - x * x) * np.polyval(c32.astype(np.float64)[::-1], x * x)
-    exact = np.cos(np.pi * x)
-    nz = np.abs(x) < 0.5
-    rel = np.abs(approx[nz] - exact[nz]) / np.abs(exact[nz])
-    print(f"cos: minimax relative error {level:.3e}; with FP32 coefficients {rel.max():.3e}")
+    err = np.abs(np.polyval(c32.astype(np.float64)[::-1], x * x) - np.cos(np.pi * x))
+    print(f"cos: minimax absolute error {level:.3e}; with FP32 coefficients {err.max():.3e}")
     for k, c in enumerate(c32):
-        print(f"kCosR{k} = {float(c).hex()}f  // {float(c)!r}")
+        print(f"kCosPi{k} = {float(c).hex()}f  // {float(c)!r}")
 
 
 if __name__ == "__main__":

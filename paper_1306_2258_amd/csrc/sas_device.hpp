@@ -110,72 +110,64 @@ __device__ __forceinline__ float parity_sign(double k) {
   return __uint_as_float(bits ^ 0x3f800000u);
 }
 
-// ---------------------------------------------------------------------------
-// Direct evaluation of sin(q r) (and cos(q r)) for any q, from rp = r / pi:
-// the direct forms (any q grid) and the orientation average's per-q path.
-//
-// t = q rp is reduced modulo 2 by one FP64 FMA.  Adding 1.5 * 2^21 puts the
-// sum in [2^21, 2^22) for |t| < 2^20 (|q r| below 3.2e6 rad), where its last
-// significand bit is worth 2^-31: the FMA rounds t to a multiple of 2^-31 (to
-// nearest, so without bias) and the low 32 bits of the sum's significand hold
-// t 2^31 modulo 2^32.  Read as a signed integer that is z 2^31 with
-// z = t mod 2 in [-1, 1), and sin(q r) = sin(pi z); the conversion to FP32
-// rounds once more (to nearest).  With a = |z| - 1/2 in [-1/2, 1/2]:
-//     sin(pi z) = sign(z) cos(pi a) = sign(z) (1/4 - a^2) R(a^2),
-//     cos(pi z) = -sin(pi a)        = -a P(a^2),
-// with R and P the degree-4 minimax fits for relative error (7e-9 and 4e-8
-// with FP32 coefficients; fit_sinpi.py beside this file reproduces them).
-// The sine costs one FP64 FMA and ten FP32 operations, the pair one FP64 FMA
-// and fifteen.
-// ---------------------------------------------------------------------------
-constexpr double kMod2Magic = 0x1.8p+21;
+// Direct form: acc + sin(q r) * w, for any q >= 0, from rp = r / pi.
+// t = q * rp is rounded to the nearest integer k by adding 1.5 * 2^52 in the
+// same FMA (the sum's low word then holds k), x = t - k lies in [-1/2, 1/2]
+// and is exact to FP64 rounding, and sin(q r) = (-1)^k sin(pi x) =
+// sin(pi (-1)^k x): the parity of k flips the sign bit of x.  sin(pi x) is
+// x * P(x^2) with P the degree-4 minimax fit of relative error 5e-9
+// (coefficients rounded to FP32, 4e-8; fit_sinpi.py beside this file
+// reproduces them and the cosine's below).  Four FP64 and eight FP32
+// instructions per call.
+constexpr double kRoundMagic = 0x1.8p+52;
 constexpr float kSinPi0 = 0x1.921fb6p+1f, kSinPi1 = -0x1.4abbc2p+2f, kSinPi2 = 0x1.4668b0p+1f,
                 kSinPi3 = -0x1.324ccap-1f, kSinPi4 = 0x1.3daff6p-4f;
-constexpr float kCosR0 = 0x1.000000p+2f, kCosR1 = -0x1.de9e5ep+1f, kCosR2 = 0x1.472a56p+0f,
-                kCosR3 = -0x1.d474dcp-3f, kCosR4 = 0x1.8bbd5ap-6f;
 
-// z 2^31 in FP32 for t = q rp (see above).
-__device__ __forceinline__ float mod2_scaled(double q, double rp) {
-  const double s = fma(q, rp, kMod2Magic);
-  return static_cast<float>(__double2loint(s));
-}
+constexpr float kCosPi0 = 0x1.000000p+0f, kCosPi1 = -0x1.3bd3ccp+2f, kCosPi2 = 0x1.03c1e4p+2f,
+                kCosPi3 = -0x1.55d076p+0f, kCosPi4 = 0x1.e126f2p-3f, kCosPi5 = -0x1.8fb73ep-6f;
 
-// R(y) and P(y) of the comment above.
-__device__ __forceinline__ float poly_cos_r(float y) {
-  float r = fmaf(y, kCosR4, kCosR3);
-  r = fmaf(r, y, kCosR2);
-  r = fmaf(r, y, kCosR1);
-  return fmaf(r, y, kCosR0);
-}
-__device__ __forceinline__ float poly_sin_p(float y) {
-  float p = fmaf(y, kSinPi4, kSinPi3);
-  p = fmaf(p, y, kSinPi2);
-  p = fmaf(p, y, kSinPi1);
-  return fmaf(p, y, kSinPi0);
-}
-
-// acc + w sin(q r).
-__device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
-  const float z = mod2_scaled(q, rp);
-  const float a = fmaf(fabsf(z), 0x1p-31f, -0.5f);
-  const float y = a * a;
-  const float es = copysignf(0.25f - y, z);
-  return fmaf(es * w, poly_cos_r(y), acc);
-}
-
-// sin(q r) and cos(q r) in FP32 (the direct adjoint, the orientation average).
+// sin(q r) and cos(q r) in FP32 for the direct adjoint, by the same reduction:
+// sin(q r) = sin(pi (-1)^k x), cos(q r) = (-1)^k cos(pi x), cos(pi x) = Q(x^2)
+// with Q the degree-5 minimax fit of absolute error 2e-10 (2e-8 with FP32
+// coefficients).
 struct SinCosF {
   float s, c;
 };
 
 __device__ __forceinline__ SinCosF sincos_qr(double q, double rp) {
-  const float z = mod2_scaled(q, rp);
-  const float a = fmaf(fabsf(z), 0x1p-31f, -0.5f);
-  const float y = a * a;
+  const double s = fma(q, rp, kRoundMagic);
+  const double k = s - kRoundMagic;
+  const float x = static_cast<float>(fma(q, rp, -k));
+  const unsigned flip = static_cast<unsigned>(__double2loint(s)) << 31;
+  const float xs = __uint_as_float(__float_as_uint(x) + flip);
+  const float y = x * x;
+  float p = fmaf(y, kSinPi4, kSinPi3);
+  p = fmaf(p, y, kSinPi2);
+  p = fmaf(p, y, kSinPi1);
+  p = fmaf(p, y, kSinPi0);
+  float c = fmaf(y, kCosPi5, kCosPi4);
+  c = fmaf(c, y, kCosPi3);
+  c = fmaf(c, y, kCosPi2);
+  c = fmaf(c, y, kCosPi1);
+  c = fmaf(c, y, kCosPi0);
   SinCosF r;
-  r.s = copysignf(0.25f - y, z) * poly_cos_r(y);
-  r.c = -a * poly_sin_p(y);
+  r.s = xs * p;
+  r.c = __uint_as_float(__float_as_uint(c) + flip);
   return r;
+}
+
+__device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
+  const double s = fma(q, rp, kRoundMagic);
+  const double k = s - kRoundMagic;
+  const float x = static_cast<float>(fma(q, rp, -k));
+  const unsigned lo = static_cast<unsigned>(__double2loint(s));
+  const float xs = __uint_as_float(__float_as_uint(x) + (lo << 31));
+  const float y = xs * xs;
+  float p = fmaf(y, kSinPi4, kSinPi3);
+  p = fmaf(p, y, kSinPi2);
+  p = fmaf(p, y, kSinPi1);
+  p = fmaf(p, y, kSinPi0);
+  return fmaf(xs * w, p, acc);
 }
 
 }  // namespace sas

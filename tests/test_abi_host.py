@@ -139,10 +139,10 @@ def test_binding_q_grid_check():
 
 
 def test_sine_polynomial_constants_match_their_fit():
-    """The direct form's FP32 coefficients in sas_device.hpp are the ones the
-    committed Remez fit produces: sin(pi x) = x P(x^2) to 5e-8 relative and
-    cos(pi x) = (1/4 - x^2) R(x^2) to 1e-8 relative on |x| < 1/2 (evaluated
-    in FP64 here)."""
+    """The direct form's FP32 sine and cosine coefficients in sas_device.hpp
+    are the ones the committed Remez fit produces, and they reach 5e-8
+    relative (sine) and 3e-8 absolute (cosine) on |x| <= 1/2 (evaluated in
+    FP64 here)."""
     import importlib.util
     import re
 
@@ -150,53 +150,27 @@ def test_sine_polynomial_constants_match_their_fit():
     spec = importlib.util.spec_from_file_location("fit_sinpi", os.path.join(root, "fit_sinpi.py"))
     fit = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(fit)
-    src = open(os.path.join(root, "sas_device.hpp")).read()
-    x = np.linspace(-0.5, 0.5, 100001)
     coef, level = fit.remez(fit.sin_target, 4, True)
     assert level < 1e-8
+    src = open(os.path.join(root, "sas_device.hpp")).read()
+    ccoef, clevel = fit.remez(fit.cos_target, 5, False)
+    assert clevel < 1e-9
+    cfound = {int(k): float.fromhex(v) for k, v in re.findall(r"kCosPi(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
+    assert sorted(cfound) == [0, 1, 2, 3, 4, 5]
+    cc32 = np.array([cfound[k] for k in range(6)])
+    assert np.array_equal(cc32, ccoef.astype(np.float32).astype(np.float64))
+    xx = np.linspace(-0.5, 0.5, 100001)
+    assert np.max(np.abs(np.polyval(cc32[::-1], xx * xx) - np.cos(np.pi * xx))) < 3e-8
     found = {int(k): float.fromhex(v) for k, v in re.findall(r"kSinPi(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
     assert sorted(found) == [0, 1, 2, 3, 4]
     c32 = np.array([found[k] for k in range(5)])
     assert np.array_equal(c32, coef.astype(np.float32).astype(np.float64))
+    x = np.linspace(-0.5, 0.5, 100001)
     approx = x * np.polyval(c32[::-1], x * x)
     exact = np.sin(np.pi * x)
     nz = exact != 0
     assert np.max(np.abs(approx[nz] - exact[nz]) / np.abs(exact[nz])) < 5e-8
-    rcoef, rlevel = fit.remez(fit.cos_target, 4, True)
-    assert rlevel < 1e-9
-    rfound = {int(k): float.fromhex(v) for k, v in re.findall(r"kCosR(\d) = (-?0x[0-9a-fp.+-]+)f", src)}
-    assert sorted(rfound) == [0, 1, 2, 3, 4]
-    r32 = np.array([rfound[k] for k in range(5)])
-    assert np.array_equal(r32, rcoef.astype(np.float32).astype(np.float64))
-    inner = np.abs(x) < 0.5
-    approx = (0.25 - x * x) * np.polyval(r32[::-1], x * x)
-    exact = np.cos(np.pi * x)
-    assert np.max(np.abs(approx[inner] - exact[inner]) / np.abs(exact[inner])) < 1e-8
 
-
-def test_mod2_reduction_of_the_direct_form():
-    """The direct form's reduction (sas_device.hpp, mod2_scaled): adding
-    1.5 * 2^21 to t = q r / pi in one FMA leaves, in the low 32 bits of the
-    FP64 sum, t 2^31 modulo 2^32 with t rounded to 2^-31; read as a signed
-    integer, z = lo 2^-31 is t mod 2 in [-1, 1), so sin(pi z) = sin(q r).
-    Checked here in extended precision for |q r| up to 3e6 rad (the fused
-    product is exact to 2^-64 relative in long double)."""
-    rng = np.random.default_rng(5)
-    q = np.concatenate([rng.uniform(0, 1.0, 200000), rng.uniform(0, 2e4, 200000), [0.0, 0.25, 0.5]])
-    r = np.concatenate([rng.uniform(0, 3400.0, 200000), rng.uniform(0, 60.0, 200000), [1.0, 4.0, 2.0]])
-    rp = r / np.pi
-    t = q.astype(np.longdouble) * rp.astype(np.longdouble)
-    assert np.max(np.abs(t)) < 2.0 ** 20
-    s = (t + np.longdouble(1.5 * 2.0 ** 21)).astype(np.float64)
-    lo = (s.view(np.uint64) & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)
-    z = lo.astype(np.float64) * 2.0 ** -31
-    assert np.all((z >= -1.0) & (z < 1.0))
-    want = np.mod(t + 1, 2).astype(np.float64) - 1.0  # t mod 2 in [-1, 1)
-    d = np.abs(z - want)
-    d = np.minimum(d, 2.0 - d)  # the wrap at +-1 is one point
-    assert d.max() <= 2.0 ** -31
-    exact = np.sin((q.astype(np.longdouble) * r.astype(np.longdouble))).astype(np.float64)
-    assert np.max(np.abs(np.sin(np.pi * z) - exact)) < 2e-9
 
 def test_orient_degree_rule(lib):
     """The quadrature degree grows with q R, is at least 0.6 digits + q R,

@@ -308,3 +308,25 @@ def test_forced_direct_form_applies_to_both_gradients(sd):
     got_t = gt.cpu().numpy()
     err = np.linalg.norm(got_t - ref_t, axis=1) / np.linalg.norm(ref_t, axis=1)
     assert err.max() <= GTOL, err
+
+
+def test_direct_form_keeps_relative_accuracy_at_tiny_qr(sd):
+    """sinc(x) and its derivative divide sin(x) by x, so the direct form's
+    sine must be accurate relative to its value as q r -> 0, not only in
+    absolute terms: a log grid from q = 1e-6 on a two-atom pair at 1 A and a
+    300-atom molecule, profile and gradient against the oracle."""
+    import torch
+
+    say("direct form at tiny q r: log grid [1e-6, 0.3]")
+    q = W.log_grid(1e-6, 0.3, 48)
+    pair = W.Molecule("pair", np.array([[0.0, 0.0, 0.0], [0.6, 0.8, 0.0]], dtype=np.float32),
+                      np.array([0, 1], dtype=np.int32), W.gaussian_table((6.0, 8.0), (0.5, 1.1), q), q)
+    mol = W.random_molecule(798, 300, 0, t=3, q=q, extent=12.0)
+    for m in (pair, mol):
+        got = gpu_profile(sd, m)
+        ref = oracle.profile(m.coords, m.types, m.table, m.q)
+        err = np.max(np.abs(got - ref) / ref)
+        print(f"{m.name}: profile max rel err {err:.3e}")
+        assert err <= 1e-6
+        w = np.random.default_rng(19).normal(size=len(q)) * (1.0 + 1.0 / q) / 1e6
+        _grad_check(sd, m, w)
