@@ -158,9 +158,12 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
 
 /*
  * Batched plan: binds the device buffers above once, chooses the tile shape by
- * timing candidate variants on first execution (the choice is cached in the
- * context per workload shape), captures the launch sequence in a hipGraph and
- * replays it on each execute.  The caller may rewrite coords/types/table in
+ * timing candidate variants on first execution (J blocks of 64, 128, 256 and
+ * 512 atoms, the default q chunk and half of it, grid and persistent launch
+ * of the pair kernel; the choice is cached in the context per workload shape;
+ * with SAS_TUNE_LOG set in the environment when the context is created, every
+ * timing is printed to stderr), captures the launch sequence in a hipGraph
+ * and replays it on each execute.  The caller may rewrite coords/types/table in
  * place between executes; sizes, offsets and q are fixed at creation.
  * The plan must be destroyed before the context.
  */
@@ -265,10 +268,13 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
 /*
  * Tuning controls (optional).  sas_set_variant forces the forward tile shape
  * for subsequent calls on ctx: bj = atoms per J block (64, 128, 256 or 512;
- * 0 = automatic) and qc = q values per chunk (one of 16, 32, 64, 100, 128,
- * 200; 0 = automatic; a non-uniform grid always uses chunks of at most 32).
- * Returns SAS_ERR_INVALID_ARG for other values.
- * sas_get_variant reports the shape the last forward call used.
+ * 0 = automatic) and qc = q values per chunk (one of 16, 32, 50, 64, 100,
+ * 128, 150, 200: chunks of qc values, the last one shorter; 0 = automatic:
+ * balanced chunks of at most 200; a non-uniform grid always uses chunks of
+ * at most 32).  Returns SAS_ERR_INVALID_ARG for other values.
+ * sas_get_variant reports the shape the last forward call (or plan) used;
+ * passing it back to sas_set_variant reproduces that call's chunks, and so
+ * its results bit for bit.
  */
 sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc);
 sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
@@ -281,17 +287,27 @@ sas_status sas_get_variant(const sas_ctx* ctx, int32_t* bj, int32_t* qc);
  * directly, one sine per pair and q as in the paper's per-q kernel
  * (Implementation section), which measures what the recurrence saves.
  * SAS_FORM_PER_ATOM weights every pair term by f_j inside the q loop even
- * for few types.  sas_get_form reports the form the last profile call used:
- * SAS_FORM_RECURRENCE or SAS_FORM_DIRECT, plus SAS_FORM_PER_ATOM when set.
+ * for few types.  The pair kernel of the recurrence's type form has two
+ * launches with bitwise the same results: a grid of one work-group per strip
+ * of pair tiles, and a persistent grid (as many one-wave work-groups as the
+ * GPU holds at once, each pulling the next strip from a counter in the
+ * workspace).  By default calls on one structure use the persistent launch,
+ * eager batched calls the grid, and a batched plan times both and keeps the
+ * faster; SAS_FORM_PERSISTENT or SAS_FORM_GRID forces one (the other forms
+ * ignore both).  sas_get_form reports the form the last profile or gradient
+ * call (or plan) used: SAS_FORM_RECURRENCE or SAS_FORM_DIRECT, plus
+ * SAS_FORM_PER_ATOM and SAS_FORM_PERSISTENT when they applied.
+ * Errors: SAS_ERR_INVALID_ARG (NULL, unknown flags, both launch flags).
  * Both gradients (sas_debye_grad, sas_debye_grad_table) follow the same
  * flags: the direct variants on non-uniform grids or with SAS_FORM_DIRECT,
  * the per-atom variants with many table rows or SAS_FORM_PER_ATOM.
- * Errors: SAS_ERR_INVALID_ARG (NULL, unknown flags).
  */
 #define SAS_FORM_AUTO 0
 #define SAS_FORM_DIRECT 1
 #define SAS_FORM_RECURRENCE 2
 #define SAS_FORM_PER_ATOM 4
+#define SAS_FORM_PERSISTENT 8
+#define SAS_FORM_GRID 16
 sas_status sas_set_form(sas_ctx* ctx, int form);
 sas_status sas_get_form(const sas_ctx* ctx, int* form);
 

@@ -32,7 +32,8 @@ from . import _lib
 from ._lib import SasError, check, load
 
 __all__ = [
-    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched", "debye_grad", "debye_grad_table",
+    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched",
+    "debye_grad", "debye_grad_table",
     "debye_profile_hybrid", "orient_degree",
     "BatchedPlan", "DebyeProfile", "debye_profile_autograd", "default_context",
 ]
@@ -103,21 +104,34 @@ class Context:
         check(load().sas_get_variant(self._h, ctypes.byref(bj), ctypes.byref(qc)), "sas_get_variant")
         return bj.value, qc.value
 
-    FORMS = {"auto": 0, "direct": 1, "per_atom": 4, "direct+per_atom": 5}
+    FORMS = {"auto": 0, "direct": 1, "per_atom": 4, "persistent": 8, "grid": 16}
 
     def set_form(self, form: str = "auto") -> None:
         """'direct' evaluates every grid by one sine per pair and q;
-        'per_atom' weights every pair term by f_j inside the q loop; 'auto'
-        (default) uses the recurrence on uniform grids and chooses between
-        the type-sorted and the per-atom form from T and the atom counts."""
-        check(load().sas_set_form(self._h, self.FORMS[form]), "sas_set_form")
+        'per_atom' weights every pair term by f_j inside the q loop;
+        'persistent' and 'grid' force the launch of the recurrence's pair
+        kernel (a persistent grid pulling strips from a counter, or one
+        work-group per strip; by default single structures use the first);
+        'auto' (default) uses the recurrence on uniform grids and chooses
+        between the type-sorted and the per-atom form from T and the atom
+        counts.  Forms combine with '+' ('direct+per_atom')."""
+        flags = 0
+        for part in form.split("+"):
+            flags |= self.FORMS[part]
+        check(load().sas_set_form(self._h, flags), "sas_set_form")
 
     def form(self) -> str:
-        """Form the last profile call used: 'recurrence' or 'direct', with
-        '+per_atom' appended for the per-atom form."""
+        """Form the last profile or gradient call used: 'recurrence' or
+        'direct', with '+per_atom' appended for the per-atom form."""
         f = ctypes.c_int()
         check(load().sas_get_form(self._h, ctypes.byref(f)), "sas_get_form")
         return ("direct" if f.value & 1 else "recurrence") + ("+per_atom" if f.value & 4 else "")
+
+    def launch(self) -> str:
+        """Launch of the last call's pair kernel: 'persistent' or 'grid'."""
+        f = ctypes.c_int()
+        check(load().sas_get_form(self._h, ctypes.byref(f)), "sas_get_form")
+        return "persistent" if f.value & 8 else "grid"
 
     def enable_timing(self, on: bool = True) -> None:
         """Bracket every pair-kernel launch with HIP events on its stream."""

@@ -84,12 +84,7 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   const double ir = rsqrt_f64(r2);
   const double r = r2 * ir;
   p.ir = static_cast<float>(ir);
-  const double delta = dq * r;
-  const double k = rint(delta * kOneOverPi);
-  double dp = fma(-k, kPiA, delta);
-  dp = fma(-k, kPiB, dp);
-  dp = fma(-k, kPiC, dp);
-  const SinCos hh = sincos_small(0.5 * dp);
+  const SinCos hh = half_step(0.5 * dq * r, &p.sg);
   const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
   const double lam = s2 * s2;     // 4 sin^2(dp/2)
   const double sdp = s2 * hh.c;   // sin(dp)
@@ -107,7 +102,6 @@ __device__ __forceinline__ AdjSeed adj_seed(const double4& pi, const double4& pj
   p.z = static_cast<float>(S0);
   p.d = static_cast<float>(fma(C0, sdp, -S0 * omc));
   p.nlam = static_cast<float>(-lam);
-  p.sg = parity_sign(k);
   return p;
 }
 

@@ -55,7 +55,11 @@ struct sas_ctx {
   int32_t force_bj = 0, force_qc = 0;
   bool force_direct = false;    // evaluate every grid by the direct form
   bool force_per_atom = false;  // per-atom form factors whatever T
-  bool last_direct = false, last_per_atom = false;
+  // pair-kernel launch of the recurrence's type form: 0 automatic (persistent
+  // for one structure, the faster by timing in a plan, a grid for eager
+  // batched calls), 1 persistent, 2 grid
+  int launch = 0;
+  bool last_direct = false, last_per_atom = false, last_persist = false;
   int32_t last_bj = 0, last_qc = 0;
   // pinned staging for the host-written blocks (descriptors of a batched
   // call, a non-uniform q grid, the orientation rule): a ring of slots, each
@@ -70,7 +74,12 @@ struct sas_ctx {
   int stage_next = 0;
   std::mutex mu;
   // tile shape (bj, qc) chosen by timing, per workload key; filled by plans
-  std::map<std::string, std::pair<int32_t, int32_t>> tuned;
+  struct Tile {
+    int32_t bj = 0, qc = 0;  // 0: the schedule's default
+    bool persist = false;
+  };
+  std::map<std::string, Tile> tuned;
+  bool tune_log = false;  // SAS_TUNE_LOG: print every timed candidate to stderr
   // optional kernel timing: event pairs around pair-kernel launches
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
@@ -136,6 +145,7 @@ struct Schedule {
   Geometry geo{};
   bool direct = false;    // arbitrary q grid: per-q evaluation instead of the recurrence
   bool per_atom = false;  // f_j inside the pair loop, no type sort
+  bool persist = false;   // persistent pair-kernel launch with a work counter
   int32_t tg_types = 0;   // > 0: the forward also writes per-type table-gradient rows
   int32_t qc = 0, qc_template = 0;
   int32_t nchunks = 0, ldt = 0;  // q chunks; row stride of the padded table
@@ -156,6 +166,7 @@ struct Layout {
   size_t gI = 0, gJ = 0, total = 0;
   size_t asum = 0;  // per-atom form: per pack block sums of f and f^2
   size_t gpart = 0, gslices = 0;  // table gradient: [strips][T][Nq], [slices][T][Nq]
+  size_t counter = 0;             // persistent launch: the work counter
   // host-written block, uploaded in one copy: structure descriptors (S > 1)
   // followed by the q grid (direct form)
   size_t upload = 0, upload_bytes = 0, desc = 0, qdev = 0;
@@ -209,11 +220,15 @@ int32_t default_bj(int64_t max_n) {
 // Build the schedule for structure sizes `sizes` (caller order).
 Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, int32_t T, int32_t Nq,
                        int32_t bj_override = 0, int32_t qc_override = 0, bool direct = false, bool per_atom = false,
-                       int32_t tg_types = 0) {
+                       int32_t tg_types = 0, int persist_override = -1) {
   Schedule sc;
   sc.direct = direct;
   sc.per_atom = per_atom;
   sc.tg_types = tg_types;
+  // the persistent launch exists for the recurrence's type-form profile
+  const int launch = ctx ? ctx->launch : 0;
+  sc.persist = !direct && !per_atom && tg_types == 0 &&
+               (persist_override >= 0 ? persist_override != 0 : (launch == 1 || (launch == 0 && sizes.size() == 1)));
   sc.S = static_cast<int32_t>(sizes.size());
   int64_t max_n = 0;
   for (int64_t n : sizes) {
@@ -227,13 +242,12 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
     const int32_t nch = (Nq + 31) / 32;
     qc = (Nq + nch - 1) / nch;
     sc.qc_template = 32;
-  } else if (qc_override > 0) {
-    const int32_t nch = (Nq + qc_override - 1) / qc_override;
-    qc = (Nq + nch - 1) / nch;
-    sc.qc_template = pick_qc_template(qc, per_atom);
-  } else if (ctx && ctx->force_qc > 0) {
-    qc = std::min(ctx->force_qc, Nq);
-    sc.qc_template = per_atom ? pick_qc_template(ctx->force_qc, true) : ctx->force_qc;
+  } else if (qc_override > 0 || (ctx && ctx->force_qc > 0)) {
+    // a chunk of the template's length (a tuner candidate or sas_set_variant):
+    // the shape sas_get_variant reports reproduces the same chunks
+    const int32_t fq = qc_override > 0 ? qc_override : ctx->force_qc;
+    qc = std::min(fq, Nq);
+    sc.qc_template = per_atom ? pick_qc_template(fq, true) : fq;
   } else {
     const int32_t nch = (Nq + 199) / 200;
     qc = (Nq + nch - 1) / nch;
@@ -296,17 +310,41 @@ Schedule make_schedule(const sas_ctx* ctx, const std::vector<int64_t>& sizes, in
   return sc;
 }
 
-// Tile shapes a plan may time: every J-block size with the default q chunk
-// (halving the chunk was always slower on MI355X: each chunk repeats the
-// per-pair FP64 set-up).  A forced variant is the only candidate.
-std::vector<std::pair<int32_t, int32_t>> tile_candidates(const sas_ctx* ctx, int32_t Nq) {
-  (void)Nq;
-  std::vector<std::pair<int32_t, int32_t>> out;
+// Tile shapes a plan may time: every J-block size, with the default q chunk
+// and with half of it (more waves per SIMD, but each chunk repeats the
+// per-pair FP64 set-up), each launched as a grid of one work-group per strip
+// and as a persistent grid pulling strips from a counter (recurrence, type
+// form only).  A forced variant (sas_set_variant, SAS_FORM_PERSISTENT) is the
+// only candidate.
+std::vector<sas_ctx::Tile> tile_candidates(const sas_ctx* ctx, int32_t Nq, bool direct, bool per_atom) {
+  std::vector<sas_ctx::Tile> out;
   if (ctx && (ctx->force_bj > 0 || ctx->force_qc > 0)) {
-    out.emplace_back(ctx->force_bj, ctx->force_qc);
+    sas_ctx::Tile t;
+    t.bj = ctx->force_bj;
+    t.qc = ctx->force_qc;
+    t.persist = ctx->launch != 2 && !direct && !per_atom;
+    out.push_back(t);
     return out;
   }
-  for (int32_t bj : {64, 128, 256, 512}) out.emplace_back(bj, 0);
+  // the default chunk (make_schedule): balanced chunks of at most 200 q; the
+  // other candidate is the shortest chunk template of at least half of it
+  const int32_t def_qc = (Nq + (Nq + 199) / 200 - 1) / ((Nq + 199) / 200);
+  std::vector<int32_t> qcs{0};
+  if (!direct && def_qc >= 32) {
+    const int32_t half = pick_qc_template((def_qc + 1) / 2, per_atom);
+    if (half < def_qc) qcs.push_back(half);
+  }
+  for (int32_t bj : {64, 128, 256, 512})
+    for (int32_t qc : qcs)
+      for (bool persist : {false, true}) {
+        if (persist && (direct || per_atom)) continue;
+        if (ctx && ((ctx->launch == 1 && !persist) || (ctx->launch == 2 && persist))) continue;
+        sas_ctx::Tile t;
+        t.bj = bj;
+        t.qc = qc;
+        t.persist = persist;
+        out.push_back(t);
+      }
   return out;
 }
 
@@ -383,6 +421,9 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
     L.qdev = L.upload + dbytes;
   }
   L.tabp = take(sizeof(float) * static_cast<size_t>(T) * sc.ldt);
+  // (the persistent launch's work counter; reserved for every schedule so that
+  // the workspace queries do not depend on the launch form)
+  L.counter = take(sizeof(unsigned long long));
   L.partial = take(sizeof(double) * sc.n_strips * Nq);
   L.slices = take(sizeof(double) * sc.n_slices * Nq);
   if (sc.tg_types > 0) {
@@ -533,6 +574,15 @@ sas_status stage_upload(sas_ctx* ctx, void* ws, const Layout& L, const std::vect
   return stage_upload_to(ctx, static_cast<char*>(ws) + L.upload, img, hs);
 }
 
+// Record the form and tile shape a profile call used (sas_get_form, sas_get_variant).
+void note_last(sas_ctx* ctx, const Schedule& sc) {
+  ctx->last_bj = sc.geo.bj;
+  ctx->last_qc = sc.qc_template;
+  ctx->last_direct = sc.direct;
+  ctx->last_per_atom = sc.per_atom;
+  ctx->last_persist = sc.persist;
+}
+
 // Enqueue pack -> forward -> reduce for a prepared schedule.  The upload
 // block (descriptors when S > 1, the q grid in the direct form) must already
 // be in the workspace.
@@ -551,7 +601,8 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   auto* slices = reinterpret_cast<double*>(w + L.slices);
   auto* tabp = reinterpret_cast<float*>(w + L.tabp);
   auto* asum = sc.per_atom ? reinterpret_cast<double*>(w + L.asum) : nullptr;
-  SAS_HIP(sas::launch_pad_table(table, T, Nq, sc.ldt, tabp, st));
+  auto* counter = sc.persist ? reinterpret_cast<unsigned long long*>(w + L.counter) : nullptr;
+  SAS_HIP(sas::launch_pad_table(table, T, Nq, sc.ldt, tabp, st, counter));
   if (sc.per_atom) {
     SAS_HIP(sas::launch_pack_plain(coords, types, sc.n_total, T, xyz, tsort, perm, st));
     SAS_HIP(sas::launch_atom_sums(sd, sc.n_pack, tsort, tabp, T, sc.ldt, Nq, asum, st));
@@ -575,6 +626,8 @@ sas_status enqueue_forward(sas_ctx* ctx, const Schedule& sc, const Layout& L, co
   a.dq = dq;
   a.qdev = qdev;
   a.gpart = sc.tg_types > 0 ? reinterpret_cast<double*>(w + L.gpart) : nullptr;
+  a.counter = counter;
+  a.n_work = sc.n_strips * sc.nchunks;
   {
     LaunchTimer timer(ctx, st, false);
     if (sc.per_atom)
@@ -759,6 +812,8 @@ sas_status sas_create(int device, sas_ctx** out) {
   c->cu_count = prop.multiProcessorCount;
   const char* dv = std::getenv("SAS_DEBUG_VALIDATE");
   c->debug_validate = dv && dv[0] && std::strcmp(dv, "0") != 0;
+  const char* tl = std::getenv("SAS_TUNE_LOG");
+  c->tune_log = tl && tl[0] && std::strcmp(tl, "0") != 0;
   *out = c;
   return SAS_OK;
 }
@@ -803,15 +858,20 @@ sas_status sas_set_variant(sas_ctx* ctx, int32_t bj, int32_t qc) {
 
 sas_status sas_set_form(sas_ctx* ctx, int form) {
   if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
-  if (form & ~(SAS_FORM_DIRECT | SAS_FORM_PER_ATOM)) return fail(SAS_ERR_INVALID_ARG, "unknown form %d", form);
+  if (form & ~(SAS_FORM_DIRECT | SAS_FORM_PER_ATOM | SAS_FORM_PERSISTENT | SAS_FORM_GRID))
+    return fail(SAS_ERR_INVALID_ARG, "unknown form %d", form);
+  if ((form & SAS_FORM_PERSISTENT) && (form & SAS_FORM_GRID))
+    return fail(SAS_ERR_INVALID_ARG, "SAS_FORM_PERSISTENT and SAS_FORM_GRID exclude each other");
   ctx->force_direct = (form & SAS_FORM_DIRECT) != 0;
   ctx->force_per_atom = (form & SAS_FORM_PER_ATOM) != 0;
+  ctx->launch = (form & SAS_FORM_PERSISTENT) ? 1 : ((form & SAS_FORM_GRID) ? 2 : 0);
   return SAS_OK;
 }
 
 sas_status sas_get_form(const sas_ctx* ctx, int* form) {
   if (!ctx || !form) return fail(SAS_ERR_INVALID_ARG, "NULL argument");
-  *form = (ctx->last_direct ? SAS_FORM_DIRECT : SAS_FORM_RECURRENCE) | (ctx->last_per_atom ? SAS_FORM_PER_ATOM : 0);
+  *form = (ctx->last_direct ? SAS_FORM_DIRECT : SAS_FORM_RECURRENCE) | (ctx->last_per_atom ? SAS_FORM_PER_ATOM : 0) |
+          (ctx->last_persist ? SAS_FORM_PERSISTENT : 0);
   return SAS_OK;
 }
 
@@ -918,12 +978,7 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
   st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
-  if (st == SAS_OK) {
-    ctx->last_bj = sc.geo.bj;
-    ctx->last_qc = sc.qc_template;
-    ctx->last_direct = sc.direct;
-    ctx->last_per_atom = sc.per_atom;
-  }
+  if (st == SAS_OK) note_last(ctx, sc);
   return st;
 }
 
@@ -936,10 +991,10 @@ size_t sas_debye_workspace_size_batched(const sas_ctx* ctx, const int64_t* offse
   // the direct form (the grid is not known here)
   const bool pa = use_per_atom(ctx, t, max_size(sizes));
   size_t need = make_layout(make_schedule(ctx, sizes, t, nq, 0, 0, false, pa), t, nq).total;
-  for (const auto& c : tile_candidates(ctx, nq))
-    for (bool direct : {false, true})
-      need = std::max(need,
-                      make_layout(make_schedule(ctx, sizes, t, nq, c.first, c.second, direct, pa), t, nq).total);
+  for (bool direct : {false, true})
+    for (const auto& c : tile_candidates(ctx, nq, direct, pa))
+      need = std::max(need, make_layout(make_schedule(ctx, sizes, t, nq, c.bj, c.qc, direct, pa, 0, c.persist ? 1 : 0),
+                                        t, nq).total);
   return need;
 }
 
@@ -974,12 +1029,7 @@ sas_status sas_debye_profile_batched(sas_ctx* ctx, const float* coords, const in
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
   st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
-  if (st == SAS_OK) {
-    ctx->last_bj = sc.geo.bj;
-    ctx->last_qc = sc.qc_template;
-    ctx->last_direct = sc.direct;
-    ctx->last_per_atom = sc.per_atom;
-  }
+  if (st == SAS_OK) note_last(ctx, sc);
   return st;
 }
 
@@ -1019,15 +1069,16 @@ sas_status upload_sync(const Schedule& sc, const Layout& L, const QGrid& g, void
 
 // Times every candidate tile shape on the plan's own buffers (one warm-up and
 // two timed evaluations each, HIP events on `st`) and returns the fastest.
-sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
-  const auto cands = tile_candidates(p->ctx, p->Nq);
+sas_status tune_plan(sas_plan* p, hipStream_t st, sas_ctx::Tile* best_tile) {
+  const auto cands = tile_candidates(p->ctx, p->Nq, p->direct, p->per_atom);
   float best = -1.f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   SAS_HIP(hipEventCreate(&e0));
   SAS_HIP(hipEventCreate(&e1));
   sas_status status = SAS_OK;
   for (const auto& c : cands) {
-    const Schedule sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.first, c.second, p->direct, p->per_atom);
+    const Schedule sc =
+        make_schedule(p->ctx, p->sizes, p->T, p->Nq, c.bj, c.qc, p->direct, p->per_atom, 0, c.persist ? 1 : 0);
     const Layout L = make_layout(sc, p->T, p->Nq);
     if (L.total > p->ws_bytes) continue;
     status = upload_sync(sc, L, p->grid, p->ws);
@@ -1048,10 +1099,13 @@ sas_status tune_plan(sas_plan* p, hipStream_t st, int32_t* bj, int32_t* qc) {
       status = fail(SAS_ERR_HIP, "tuning timer: %s", hipGetErrorString(e));
       break;
     }
+    if (p->ctx->tune_log)
+      std::fprintf(stderr, "sas tune: bj %d qc %d (template %d) %s: %.4f ms per evaluation\n", sc.geo.bj, sc.qc,
+                   sc.qc_template, sc.persist ? "persistent" : "grid", ms / 2);
     if (best < 0.f || ms < best) {
       best = ms;
-      *bj = sc.geo.bj;
-      *qc = c.second;
+      *best_tile = c;
+      best_tile->bj = sc.geo.bj;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1122,21 +1176,23 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
   }
   if (!p->ready) {
     // choose the tile shape: forced variant, cached choice, or timing
-    int32_t bj = 0, qc = 0;
-    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->direct ? "d" : "u") + (p->per_atom ? "a" : "t");
+    sas_ctx::Tile tile;
+    const std::string key = workload_key(p->sizes, p->T, p->Nq) + (p->direct ? "d" : "u") + (p->per_atom ? "a" : "t") +
+                            (p->ctx->launch == 1 ? "p" : (p->ctx->launch == 2 ? "g" : ""));
     const bool forced = p->ctx->force_bj > 0 || p->ctx->force_qc > 0;
     auto it = p->ctx->tuned.find(key);
     if (forced) {
-      bj = p->ctx->force_bj;
+      tile.bj = p->ctx->force_bj;
+      tile.persist = p->ctx->launch != 2 && !p->direct && !p->per_atom;
     } else if (it != p->ctx->tuned.end()) {
-      bj = it->second.first;
-      qc = it->second.second;
+      tile = it->second;
     } else {
-      sas_status st = tune_plan(p, hs, &bj, &qc);
+      sas_status st = tune_plan(p, hs, &tile);
       if (st != SAS_OK) return st;
-      p->ctx->tuned[key] = {bj, qc};
+      p->ctx->tuned[key] = tile;
     }
-    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, bj, qc, p->direct, p->per_atom);
+    p->sc = make_schedule(p->ctx, p->sizes, p->T, p->Nq, tile.bj, tile.qc, p->direct, p->per_atom, 0,
+                          tile.persist ? 1 : 0);
     p->L = make_layout(p->sc, p->T, p->Nq);
     if (p->L.total > p->ws_bytes)
       return fail(SAS_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", p->ws_bytes, p->L.total);
@@ -1157,8 +1213,7 @@ sas_status sas_plan_execute(sas_plan* p, void* stream) {
     p->graph = graph;
     SAS_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     p->ready = true;
-    p->ctx->last_bj = p->sc.geo.bj;
-    p->ctx->last_qc = p->sc.qc_template;
+    note_last(p->ctx, p->sc);
   }
   SAS_HIP(hipGraphLaunch(p->exec, hs));
   return SAS_OK;
@@ -1198,8 +1253,14 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
     hipStream_t hs = static_cast<hipStream_t>(stream);
     st = debug_validate(ctx, coords, types, n, t, hs);
     if (st != SAS_OK) return st;
-    return enqueue_table_grad_by_atom(ctx, R, coords, types, n, table, t, nq, grid, dL_dI, grad_table_out, I_out,
-                                      workspace, hs);
+    st = enqueue_table_grad_by_atom(ctx, R, coords, types, n, table, t, nq, grid, dL_dI, grad_table_out, I_out,
+                                    workspace, hs);
+    if (st == SAS_OK) {
+      ctx->last_direct = !grid.uniform || ctx->force_direct;
+      ctx->last_per_atom = true;
+      ctx->last_persist = false;
+    }
+    return st;
   }
   const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, !grid.uniform || ctx->force_direct,
                                     false, t);
@@ -1224,6 +1285,7 @@ sas_status sas_debye_grad_table(sas_ctx* ctx, const float* coords, const int32_t
                                     t * nq, gslices, hs));
   SAS_HIP(sas::launch_table_grad_final(sc.n_slices, gslices, reinterpret_cast<const int32_t*>(w + L.toff), table, t, nq,
                                        grid.q0, grid.dq, qdev, dL_dI, grad_table_out, hs));
+  note_last(ctx, sc);
   return SAS_OK;
 }
 
@@ -1304,6 +1366,7 @@ sas_status sas_debye_grad(sas_ctx* ctx, const float* coords, const int32_t* type
       SAS_HIP(sas::launch_adjoint(a, sc.nchunks_adj, hs));
   }
   SAS_HIP(sas::launch_grad_reduce(a, n, sc.nchunks_adj, reinterpret_cast<const int32_t*>(w + L.perm), grad_out, hs));
+  note_last(ctx, sc);
   return SAS_OK;
 }
 

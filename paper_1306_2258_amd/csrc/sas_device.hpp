@@ -1,44 +1,42 @@
 // Device-side helpers shared by the Debye kernels (gfx950).
 //
 // FP64 trigonometry for the per-pair set-up of the q recurrence.  The set-up
-// runs once per atom pair and q chunk, the recurrence itself runs in FP32, so
-// these helpers favour clear, branch-free FP64 code over speed:
-//   * sin/cos on |x| <= pi/4 by their Taylor series in Horner form;
-//   * additive range reduction by Cody & Waite (1980) with pi/2 and pi split
-//     into three parts of 33 significant bits each, so k * part is exact for
-//     |k| < 2^20 (|argument| < 1.6e6 rad).
+// runs once per atom pair and q chunk, the recurrence itself runs in FP32, and
+// every value the set-up produces is rounded to FP32 once, so these helpers
+// need relative accuracy well below FP32's 6e-8, not full FP64:
+//   * sin/cos on |x| <= pi/4 by minimax polynomials of relative error 5e-12
+//     and 7e-11 (fit_halfangle.py beside this file derives them);
+//   * additive range reduction by Cody & Waite (1980) with pi/2 split into
+//     parts of 33 significant bits, so k * part is exact for |k| < 2^20; the
+//     quotient k comes from one FMA that adds 1.5 * 2^52, which leaves k in
+//     the low word of the sum (its parity without a conversion).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sas {
 
-// pi/2 = kPio2A + kPio2B + kPio2C (each part rounded to 33 bits); pi = 2 x that.
+// pi/2 = kPio2A + kPio2B + kPio2C (each part rounded to 33 bits).
 constexpr double kPio2A = 0x1.921fb54400000p+0;
 constexpr double kPio2B = 0x1.0b4611a600000p-34;
 constexpr double kPio2C = 0x1.3198a2e037073p-69;
-constexpr double kPiA = 0x1.921fb54400000p+1;
-constexpr double kPiB = 0x1.0b4611a600000p-33;
-constexpr double kPiC = 0x1.3198a2e037073p-68;
 constexpr double kTwoOverPi = 0x1.45f306dc9c883p-1;
 constexpr double kOneOverPi = 0x1.45f306dc9c883p-2;
 constexpr double kTwoPi = 0x1.921fb54442d18p+2;
-
-// 1/n! for the Taylor coefficients (n! is exact in FP64 up to 22!).
-constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+// Adding 1.5 * 2^52 rounds a double of magnitude below 2^51 to an integer k
+// and leaves k (two's complement) in the low word of the sum.
+constexpr double kRoundMagic = 0x1.8p+52;
 
 struct SinCos {
   double s, c;
 };
 
-// Taylor coefficients, evaluated at compile time.  Terms through x^11 (sin)
-// and x^12 (cos) leave a truncation below 1e-11 relative for |x| <= pi/4;
-// every value derived from them is rounded to FP32 (6e-8) afterwards, so the
-// truncation adds no measurable bias.
-constexpr double kS3 = -1.0 / fact(3), kS5 = 1.0 / fact(5), kS7 = -1.0 / fact(7), kS9 = 1.0 / fact(9);
-constexpr double kS11 = -1.0 / fact(11);
-constexpr double kC2 = -1.0 / fact(2), kC4 = 1.0 / fact(4), kC6 = -1.0 / fact(6), kC8 = 1.0 / fact(8);
-constexpr double kC10 = -1.0 / fact(10), kC12 = 1.0 / fact(12);
+// sin(x) = x + x y P(y), cos(x) = 1 + y Q(y), y = x^2, on |x| <= pi/4 (1 + 1e-4):
+// minimax coefficients of P and Q (fit_halfangle.py).
+constexpr double kHs1 = -0x1.5555554c6ffb7p-3, kHs2 = 0x1.111108690b3d5p-7, kHs3 = -0x1.a00f7e144cf98p-13,
+                 kHs4 = 0x1.6cd1b07f8e9f5p-19;
+constexpr double kHc1 = -0x1.ffffffcb77e03p-2, kHc2 = 0x1.55553c74b32fap-5, kHc3 = -0x1.6c07efdea28fcp-10,
+                 kHc4 = 0x1.991642d7d2148p-16;
 
 // a * b + c with the constant c taken from an SGPR pair.  Written as inline
 // assembly because the compiler otherwise keeps every FP64 polynomial
@@ -60,39 +58,57 @@ __device__ __forceinline__ double add_vs(double a, double b) {
   return r;
 }
 
-// sin and cos of |x| <= pi/4.
+// sin and cos of |x| <= pi/4 (1 + 1e-4).
 __device__ __forceinline__ SinCos sincos_small(double x) {
-  const double x2 = x * x;
-  double ps = add_vs(mul_vs(x2, kS11), kS9);
-  ps = fma_vvs(ps, x2, kS7);
-  ps = fma_vvs(ps, x2, kS5);
-  ps = fma_vvs(ps, x2, kS3);
-  double pc = add_vs(mul_vs(x2, kC12), kC10);
-  pc = fma_vvs(pc, x2, kC8);
-  pc = fma_vvs(pc, x2, kC6);
-  pc = fma_vvs(pc, x2, kC4);
-  pc = fma_vvs(pc, x2, kC2);
+  const double y = x * x;
+  double ps = add_vs(mul_vs(y, kHs4), kHs3);
+  ps = fma_vvs(ps, y, kHs2);
+  ps = fma_vvs(ps, y, kHs1);
+  double pc = add_vs(mul_vs(y, kHc4), kHc3);
+  pc = fma_vvs(pc, y, kHc2);
+  pc = fma_vvs(pc, y, kHc1);
   SinCos r;
-  r.s = fma(x * x2, ps, x);
-  r.c = fma(x2, pc, 1.0);
+  r.s = fma(x * y, ps, x);
+  r.c = fma(y, pc, 1.0);
   return r;
+}
+
+// x = k pi/2 + h with |h| <= pi/4 (1 + 1e-4) for |x| < 1.6e6: returns h and
+// writes the quotient's low word (k mod 2^32) to *klo.  Two parts of pi/2
+// for the set-up's step angles (|k| < 2^20; the third part changes h by
+// |k| 2e-21), three for seed angles.
+template <int PARTS>
+__device__ __forceinline__ double reduce_pio2(double x, int* klo) {
+  const double s = fma(x, kTwoOverPi, kRoundMagic);
+  const double k = s - kRoundMagic;
+  double h = fma(-k, kPio2A, x);
+  h = fma(-k, kPio2B, h);
+  if constexpr (PARTS > 2) h = fma(-k, kPio2C, h);
+  *klo = __double2loint(s);
+  return h;
 }
 
 // sin and cos of any |x| < 1.6e6 (quadrant reduction by pi/2).
 __device__ __forceinline__ SinCos sincos_any(double x) {
-  const double k = rint(x * kTwoOverPi);
-  double y = fma(-k, kPio2A, x);
-  y = fma(-k, kPio2B, y);
-  y = fma(-k, kPio2C, y);
-  const SinCos b = sincos_small(y);
-  const int quad = static_cast<int>(static_cast<int64_t>(k) & 3);
+  int quad = 0;
+  const SinCos b = sincos_small(reduce_pio2<3>(x, &quad));
   SinCos r;
-  // x = y + quad * pi/2
+  // x = h + quad * pi/2
   r.s = (quad & 1) ? b.c : b.s;
   r.c = (quad & 1) ? b.s : b.c;
-  if (quad == 1 || quad == 2) r.c = -r.c;
+  if ((quad & 3) == 1 || (quad & 3) == 2) r.c = -r.c;
   if (quad & 2) r.s = -r.s;
   return r;
+}
+
+// The step angle of a pair's recurrence: for hd = dq r / 2, dq r = k pi + dp
+// with |dp| <= pi/2 (1 + 1e-4).  Returns sin and cos of dp/2 and writes
+// (-1)^k to *sg.
+__device__ __forceinline__ SinCos half_step(double hd, float* sg) {
+  int klo = 0;
+  const SinCos hh = sincos_small(reduce_pio2<2>(hd, &klo));
+  *sg = __uint_as_float((static_cast<unsigned>(klo) << 31) ^ 0x3f800000u);
+  return hh;
 }
 
 // 1/sqrt(a) for a > 0 in FP64: hardware estimate refined by one Newton step.
@@ -104,12 +120,6 @@ __device__ __forceinline__ double rsqrt_f64(double a) {
   return y * fma(-0.5 * a, y * y, 1.5);
 }
 
-// +1.0f or -1.0f for an even or odd integer k held in a double.
-__device__ __forceinline__ float parity_sign(double k) {
-  const unsigned bits = static_cast<unsigned>(static_cast<int>(k)) << 31;
-  return __uint_as_float(bits ^ 0x3f800000u);
-}
-
 // Direct form: acc + sin(q r) * w, for any q >= 0, from rp = r / pi.
 // t = q * rp is rounded to the nearest integer k by adding 1.5 * 2^52 in the
 // same FMA (the sum's low word then holds k), x = t - k lies in [-1/2, 1/2]
@@ -119,7 +129,6 @@ __device__ __forceinline__ float parity_sign(double k) {
 // (coefficients rounded to FP32, 4e-8; fit_sinpi.py beside this file
 // reproduces them and the cosine's below).  Four FP64 and eight FP32
 // instructions per call.
-constexpr double kRoundMagic = 0x1.8p+52;
 constexpr float kSinPi0 = 0x1.921fb6p+1f, kSinPi1 = -0x1.4abbc2p+2f, kSinPi2 = 0x1.4668b0p+1f,
                 kSinPi3 = -0x1.324ccap-1f, kSinPi4 = 0x1.3daff6p-4f;
 

@@ -30,24 +30,19 @@ struct PairSeed {
   float z, d, nlam, sg;
 };
 
-__device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& pj, bool use, double dq, double qs) {
+// (hdq = dq / 2, the grid step halved)
+__device__ __forceinline__ PairSeed pair_seed(const double4& pi, const double4& pj, bool use, double hdq, double qs) {
   const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   r2 = fmax(r2, 1e-60);
   const double ir = rsqrt_f64(r2);
   const double r = r2 * ir;
-  const double delta = dq * r;
-  const double k = rint(delta * kOneOverPi);
-  double dp = fma(-k, kPiA, delta);
-  dp = fma(-k, kPiB, dp);
-  dp = fma(-k, kPiC, dp);
-  const SinCos hh = sincos_small(0.5 * dp);
+  PairSeed p;
+  const SinCos hh = half_step(hdq * r, &p.sg);
   const double s2 = hh.s + hh.s;  // 2 sin(dp/2)
   const double lam = s2 * s2;     // 4 sin^2(dp/2) = 2 (1 - cos(dp))
   const double sdp = s2 * hh.c;   // sin(dp)
-  PairSeed p;
   p.nlam = static_cast<float>(-lam);
-  p.sg = parity_sign(k);
   if (qs == 0.0) {
     // chunk starting at q = 0: z_0 = 0, d_0 = sin(dp)/r
     p.z = 0.f;

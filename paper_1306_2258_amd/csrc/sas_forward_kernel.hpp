@@ -19,14 +19,16 @@
 
 namespace sas {
 
+// Waves per SIMD the forward kernels are built for.
+constexpr int forward_waves(int qc, int bj, bool direct) { return direct ? (bj >= 512 ? 2 : 5) : (qc > 128 ? 2 : 3); }
+
+// One strip t (and q chunk) of the forward pass, by the one wave of a work-group.
 template <int QC, int BJ, bool DIRECT, bool TG>
-__global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2 : 3)) void k_forward(ForwardArgs a) {
+__device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, int chunk, int lane) {
   constexpr int NG = QC / kWave;          // full groups of 64 q values
   constexpr int R = QC % kWave;           // values in the tail group
   constexpr int NT = NG + (R ? 1 : 0);    // q values owned per lane after the lane reduction
   __shared__ double4 sj[BJ];
-  const int lane = threadIdx.x;
-  const int64_t t = blockIdx.x;
   const int s = find_struct_by_strip(a.sd, t);
   const StructDesc d = a.sd.get(s);
   const StripPos sp = decode_strip(t - d.strip_off, d.n, a.geo);
@@ -37,12 +39,13 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
   const double4 pi = a.xyz[d.atom_off + ic];
   const int ta = clamp_type(a.tsort[d.atom_off + ic], a.T);
 
-  const int m0 = blockIdx.y * a.qc;
+  const int m0 = chunk * a.qc;
   const int nqc = min(a.qc, a.Nq - m0);   // <= QC; steps beyond nqc are computed and dropped
   // (the padded table tabp has ldt >= m0 + QC columns, zero beyond Nq, so no
   // per-step bounds test is needed)
   const double qs = a.q0 + m0 * a.dq;
   const double dq = a.dq;
+  const double hdq = 0.5 * dq;  // the pair set-up takes half the grid step
   const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
   const int32_t* toff = a.toff + static_cast<int64_t>(s) * (a.T + 1);
 
@@ -149,9 +152,9 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
         // each other and the QC accumulators)
         PairSeed A, B;
         if constexpr (kAhead) {
-          A = pair_seed(pi, pja, on && jl > i, dq, qs);
+          A = pair_seed(pi, pja, on && jl > i, hdq, qs);
           asm volatile("" ::: "memory");
-          B = pair_seed(pi, pjb, on && jb > i && jl + 1 < sb, dq, qs);
+          B = pair_seed(pi, pjb, on && jb > i && jl + 1 < sb, hdq, qs);
           asm volatile("" ::: "memory");
           const int jn = jl + 2 < sb ? jl + 2 : jl;
           const int jnb = jn + 1 < sb ? jn + 1 : jn;
@@ -159,9 +162,9 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
           pjb = sj[jnb - j0];
           __builtin_amdgcn_sched_barrier(0);  // keep the loads issued here
         } else {
-          A = pair_seed(pi, sj[jl - j0], on && jl > i, dq, qs);
+          A = pair_seed(pi, sj[jl - j0], on && jl > i, hdq, qs);
           asm volatile("" ::: "memory");
-          B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, dq, qs);
+          B = pair_seed(pi, sj[jb - j0], on && jb > i && jl + 1 < sb, hdq, qs);
           asm volatile("" ::: "memory");
         }
         float za = A.z, da = A.d, zb = B.z, db = B.d;
@@ -230,6 +233,78 @@ __global__ __launch_bounds__(kWave, DIRECT ? (BJ >= 512 ? 2 : 5) : (QC > 128 ? 2
     const int m = g * kWave + lane;
     if (m < nqc) out[m] = tot[g][lane];
   }
+}
+
+// One work-group per (strip, q chunk): blockIdx.x is the strip, blockIdx.y the chunk.
+template <int QC, int BJ, bool DIRECT, bool TG>
+__global__ __launch_bounds__(kWave, forward_waves(QC, BJ, DIRECT)) void k_forward(ForwardArgs a) {
+  forward_strip<QC, BJ, DIRECT, TG>(a, blockIdx.x, blockIdx.y, threadIdx.x);
+}
+
+// Persistent form: as many work-groups as fit on the GPU at once, each taking
+// the next (strip, chunk) item from a counter in device memory until all
+// a.n_work items are taken (items in strip-major order, the order of the grid
+// launch's work-groups).  The counter is zeroed by the table-padding kernel
+// that precedes every forward launch.  Each item still writes its own partial
+// row, so the result does not depend on which work-group took it.
+template <int QC, int BJ>
+__global__ __launch_bounds__(kWave, forward_waves(QC, BJ, false)) void k_forward_persist(ForwardArgs a) {
+  const int nchunks = (a.Nq + a.qc - 1) / a.qc;
+#pragma unroll 1
+  for (;;) {
+    unsigned long long w = 0;
+    if (threadIdx.x == 0) w = atomicAdd(a.counter, 1ull);
+    // broadcast from lane 0 as a wave-uniform (scalar) value, as blockIdx is
+    // in the grid launch
+    const unsigned lo = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(w));
+    const unsigned hi = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(w >> 32));
+    w = (static_cast<unsigned long long>(hi) << 32) | lo;
+    if (w >= static_cast<unsigned long long>(a.n_work)) break;
+    // (the lane index is made opaque in every iteration, so that nothing
+    // derived from it is hoisted out of this loop and held across the strip's
+    // q steps)
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    forward_strip<QC, BJ, false, false>(a, static_cast<int64_t>(w / nchunks), static_cast<int>(w % nchunks), lane);
+  }
+}
+
+// Work-groups of k_forward_persist<QC, BJ> resident on the whole GPU (the
+// occupancy query, once per template and process).
+template <int QC, int BJ>
+int64_t persist_slots() {
+  static int64_t slots = -1;
+  if (slots < 0) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_persist<QC, BJ>, kWave, 0) != hipSuccess ||
+        per_cu <= 0)
+      return 0;
+    slots = static_cast<int64_t>(per_cu) * prop.multiProcessorCount;
+  }
+  return slots;
+}
+
+template <int QC>
+hipError_t launch_forward_persist_qc(const ForwardArgs& a, hipStream_t st) {
+  int64_t slots = 0;
+  switch (a.geo.bj) {
+    case 64: slots = persist_slots<QC, 64>(); break;
+    case 128: slots = persist_slots<QC, 128>(); break;
+    case 256: slots = persist_slots<QC, 256>(); break;
+    case 512: slots = persist_slots<QC, 512>(); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (slots <= 0) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<uint32_t>(a.n_work < slots ? a.n_work : slots));
+  switch (a.geo.bj) {
+    case 64: hipLaunchKernelGGL((k_forward_persist<QC, 64>), grid, dim3(kWave), 0, st, a); break;
+    case 128: hipLaunchKernelGGL((k_forward_persist<QC, 128>), grid, dim3(kWave), 0, st, a); break;
+    case 256: hipLaunchKernelGGL((k_forward_persist<QC, 256>), grid, dim3(kWave), 0, st, a); break;
+    case 512: hipLaunchKernelGGL((k_forward_persist<QC, 512>), grid, dim3(kWave), 0, st, a); break;
+  }
+  return hipGetLastError();
 }
 
 template <int QC, bool DIRECT, bool TG>

@@ -118,8 +118,10 @@ __global__ __launch_bounds__(kPackBlock) void k_pack_scatter(const float* __rest
 
 // Copy the caller's [T][Nq] table into [T][ldt] with zeros in columns >= Nq.
 __global__ __launch_bounds__(256) void k_pad_table(const float* __restrict__ table, int32_t T, int32_t Nq,
-                                                   int32_t ldt, float* __restrict__ tabp) {
+                                                   int32_t ldt, float* __restrict__ tabp,
+                                                   unsigned long long* __restrict__ counter) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k == 0 && counter) *counter = 0ull;
   if (k >= static_cast<int64_t>(T) * ldt) return;
   const int64_t t = k / ldt;
   const int32_t m = static_cast<int32_t>(k - t * ldt);
@@ -155,10 +157,11 @@ hipError_t launch_validate(const float* coords, const int32_t* types, int64_t n,
   return hipGetLastError();
 }
 
-hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st) {
+hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st,
+                            unsigned long long* counter) {
   const int64_t total = static_cast<int64_t>(T) * ldt;
   hipLaunchKernelGGL(k_pad_table, dim3(static_cast<uint32_t>((total + 255) / 256)), dim3(256), 0, st, table, T, Nq,
-                     ldt, tabp);
+                     ldt, tabp, counter);
   return hipGetLastError();
 }
 
@@ -195,6 +198,21 @@ hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t 
   if (!geometry_ok(a.geo)) return hipErrorInvalidValue;
   const int nchunks = static_cast<int>(ceil_div(a.Nq, a.qc));
   const dim3 grid(static_cast<uint32_t>(n_strips_total), nchunks);
+  if (a.counter) {
+    // persistent launch (recurrence form only)
+    if (a.qdev || a.n_work != n_strips_total * nchunks) return hipErrorInvalidValue;
+    switch (qc_template) {
+      case 16: return launch_forward_persist_qc<16>(a, st);
+      case 32: return launch_forward_persist_qc<32>(a, st);
+      case 50: return launch_forward_persist_qc<50>(a, st);
+      case 64: return launch_forward_persist_qc<64>(a, st);
+      case 100: return launch_forward_persist_qc<100>(a, st);
+      case 128: return launch_forward_persist_qc<128>(a, st);
+      case 150: return launch_forward_persist_qc<150>(a, st);
+      case 200: return launch_forward_persist_qc<200>(a, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.qdev) {
     switch (qc_template) {
       case 32: return launch_forward_qc<32, true, false>(a, grid, st);

@@ -65,6 +65,8 @@ struct ForwardArgs {
   double* gpart;        // table gradient only: [strips][T][Nq] per-type sums
   float* rows;          // per-atom table gradient: [J blocks][rows_ld][n] per-atom sums
   int32_t rows_ld;      // q stride of rows (>= Nq)
+  unsigned long long* counter;  // persistent launch: next (strip, chunk) item; null for a grid launch
+  int64_t n_work;               // persistent launch: strips x chunks
 };
 
 constexpr int kAdjQ = 512;  // q values per adjoint chunk (weights staged in LDS)
@@ -94,7 +96,10 @@ int64_t slices_of(int64_t n_strips);
 hipError_t launch_pack(const float* coords, const int32_t* types, const DescView& sd, int32_t S,
                        int64_t n_pack_blocks, int32_t T, int32_t* bcount, int32_t* toff, double4* xyz,
                        int32_t* tsort, int32_t* perm, hipStream_t st);
-hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st);
+// Also zeroes *counter (when non-null), the work counter of a persistent
+// forward launch that follows on the same stream.
+hipError_t launch_pad_table(const float* table, int32_t T, int32_t Nq, int32_t ldt, float* tabp, hipStream_t st,
+                            unsigned long long* counter = nullptr);
 hipError_t launch_validate(const float* coords, const int32_t* types, int64_t n, int32_t T, unsigned long long* flags,
                            hipStream_t st);
 hipError_t launch_forward(const ForwardArgs& a, int64_t n_strips_total, int32_t qc_template, hipStream_t st);

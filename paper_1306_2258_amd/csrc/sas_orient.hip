@@ -38,9 +38,18 @@
 
 namespace sas {
 
-// cos(x) - 1 and sin(x) for |x| <= kRotMaxStep by the Taylor series of
-// sincos_small, without forming cos(x) itself (1 + small would lose the small
-// part's low bits).
+// cos(x) - 1 and sin(x) for |x| <= kRotMaxStep by their Taylor series, without
+// forming cos(x) itself (1 + small would lose the small part's low bits).  The
+// walk applies this increment at every step, so it keeps the series' exact
+// leading coefficients (-1/2, -1/6): relative accuracy as x -> 0.  Terms
+// through x^11 (sin) and x^12 (cos) leave a truncation below 1e-11 relative
+// for |x| <= pi/4.
+constexpr double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+constexpr double kS3 = -1.0 / fact(3), kS5 = 1.0 / fact(5), kS7 = -1.0 / fact(7), kS9 = 1.0 / fact(9);
+constexpr double kS11 = -1.0 / fact(11);
+constexpr double kC2 = -1.0 / fact(2), kC4 = 1.0 / fact(4), kC6 = -1.0 / fact(6), kC8 = 1.0 / fact(8);
+constexpr double kC10 = -1.0 / fact(10), kC12 = 1.0 / fact(12);
+
 struct StepInc {
   double cm1, s;
 };

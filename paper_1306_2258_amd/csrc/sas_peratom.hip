@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
   const int nqc = min(a.qc, a.Nq - m0);
   const double qs = a.q0 + m0 * a.dq;
   const double dq = a.dq;
+  const double hdq = 0.5 * dq;  // the pair set-up takes half the grid step
   const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
@@ -187,9 +188,9 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
         for (int jl = u0; jl < u0 + ns; jl += 2) {
           const bool two = jl + 1 < u0 + ns;
           const int jb = two ? jl + 1 : jl;
-          const PairSeed A = pair_seed(pi, sj[jl - u0], vi && (ROWS ? jl != i : jl > i), dq, qs);
+          const PairSeed A = pair_seed(pi, sj[jl - u0], vi && (ROWS ? jl != i : jl > i), hdq, qs);
           asm volatile("" ::: "memory");
-          const PairSeed B = pair_seed(pi, sj[jb - u0], vi && (ROWS ? jb != i : jb > i) && two, dq, qs);
+          const PairSeed B = pair_seed(pi, sj[jb - u0], vi && (ROWS ? jb != i : jb > i) && two, hdq, qs);
           asm volatile("" ::: "memory");
           const float4* fa4 = reinterpret_cast<const float4*>(fj[jl - u0]);
           const float4* fb4 = reinterpret_cast<const float4*>(fj[jb - u0]);

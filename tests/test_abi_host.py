@@ -172,6 +172,35 @@ def test_sine_polynomial_constants_match_their_fit():
     assert np.max(np.abs(approx[nz] - exact[nz]) / np.abs(exact[nz])) < 5e-8
 
 
+def test_half_angle_polynomial_constants_match_their_fit():
+    """The pair set-up's FP64 sine and cosine coefficients in sas_device.hpp
+    are the ones the committed Remez fit produces, and reach 6e-12 (sine)
+    and 7e-11 (cosine) relative on |x| <= pi/4, far below the single FP32
+    rounding every set-up value takes afterwards (6e-8).  Checked against
+    numpy's sin and cos here, independently of the fit's own series."""
+    import importlib.util
+    import re
+
+    root = os.path.join(os.path.dirname(__file__), "..", "paper_1306_2258_amd", "csrc")
+    spec = importlib.util.spec_from_file_location("fit_halfangle", os.path.join(root, "fit_halfangle.py"))
+    fit = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fit)
+    src = open(os.path.join(root, "sas_device.hpp")).read()
+    x = np.linspace(1e-3, np.pi / 4 * (1 + 1e-4), 200001)
+    y = x * x
+    for cos, name, bound in ((False, "kHs", 6e-12), (True, "kHc", 7e-11)):
+        coef, level = fit.remez(cos)
+        assert level < bound
+        found = {int(k): float.fromhex(v) for k, v in re.findall(name + r"(\d) = (-?0x[0-9a-fp.+-]+)", src)}
+        assert sorted(found) == [1, 2, 3, 4]
+        c = np.array([found[k] for k in range(1, 5)])
+        assert np.array_equal(c, coef)
+        poly = np.polyval(c[::-1], y)
+        approx = 1.0 + y * poly if cos else x + x * y * poly
+        exact = np.cos(x) if cos else np.sin(x)
+        assert np.max(np.abs(approx - exact) / exact) < bound + 3e-16
+
+
 def test_orient_degree_rule(lib):
     """The quadrature degree grows with q R, is at least 0.6 digits + q R,
     and rejects invalid arguments."""

@@ -119,7 +119,9 @@ def test_every_entry_point_checks(sd, dbg_ctx):
     c2, t2, tab2 = _dev(m2)
     plan = sd.BatchedPlan(c2, t2, [0, 120, 300], tab2, m2.q, ctx=dbg_ctx)
     ok = plan.execute().clone()
-    ref = sd.debye_profile_batched(c2, t2, [0, 120, 300], tab2, m2.q, ctx=sd.Context(0))
+    ref_ctx = sd.Context(0)
+    ref_ctx.set_variant(*dbg_ctx.variant())  # the tile shape the plan's tuning chose
+    ref = sd.debye_profile_batched(c2, t2, [0, 120, 300], tab2, m2.q, ctx=ref_ctx)
     assert torch.equal(ok, ref)
     c2[200, 0] = float("nan")
     with pytest.raises(sd.SasError) as e:

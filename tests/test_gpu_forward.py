@@ -338,6 +338,46 @@ def test_plan_replays_match_eager_and_oracle(sd):
     plan.close()
 
 
+@pytest.mark.parametrize("nq", [64, 200, 450])
+def test_persistent_launch_matches_grid(sd, nq):
+    """The persistent launch of the pair kernel (one-wave work-groups pulling
+    (strip, q chunk) items from a counter) gives the grid launch's results bit
+    for bit: single structures of several sizes (450 q: three chunks, so the
+    item decode walks chunks), a batched call with empty and one-atom
+    structures, repeated calls (the counter is re-zeroed each call), and the
+    launch each call reports."""
+    import torch
+
+    say(f"persistent vs grid launch, Nq={nq}")
+    grid_ctx, pers_ctx = sd.Context(0), sd.Context(0)
+    grid_ctx.set_form("grid")
+    pers_ctx.set_form("persistent")
+    auto_ctx = sd.Context(0)
+    for n in (2, 65, 700, 3000):
+        m = W.random_molecule(4000 + n + nq, n, nq, q0=0.0, q1=1.0, extent=3.0 * n ** (1 / 3) + 4)
+        a = gpu_profile(sd, m, ctx=grid_ctx)
+        assert grid_ctx.launch() == "grid"
+        for _ in range(2):
+            b = gpu_profile(sd, m, ctx=pers_ctx)
+            assert pers_ctx.launch() == "persistent"
+            assert np.array_equal(a, b), f"N={n}"
+        c = gpu_profile(sd, m, ctx=auto_ctx)
+        assert auto_ctx.launch() == "persistent" and np.array_equal(a, c)
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    assert rel_err(a, ref).max() <= TOL
+    sizes = [0, 1, 900, 130, 2, 2100, 64]
+    mols, coords, types, off = _ensemble(sizes, seed=4100, nq=nq)
+    c = torch.from_numpy(coords).cuda()
+    t = torch.from_numpy(types).cuda()
+    tab = torch.from_numpy(mols[0].table).cuda()
+    a = sd.debye_profile_batched(c, t, off, tab, mols[0].q, ctx=grid_ctx).cpu().numpy()
+    b = sd.debye_profile_batched(c, t, off, tab, mols[0].q, ctx=pers_ctx).cpu().numpy()
+    assert pers_ctx.launch() == "persistent"
+    assert np.array_equal(a, b)
+    d = sd.debye_profile_batched(c, t, off, tab, mols[0].q, ctx=auto_ctx).cpu().numpy()
+    assert auto_ctx.launch() == "grid" and np.array_equal(a, d)
+
+
 def test_plan_reuses_tuned_shape(sd):
     import torch
 
