@@ -141,6 +141,33 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
                              void* workspace, size_t ws_bytes, void* stream);
 
 /*
+ * Allocation-free variant of sas_debye_profile, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and edge cases as
+ * sas_debye_profile without the workspace: its scratch is a fixed array of
+ * SAS_NOALLOC_SCRATCH_BYTES in device memory that the library holds, one per
+ * GPU, from the first sas_create on that GPU until the process ends.  The call
+ * allocates no device or pinned memory, uploads nothing, records no kernel
+ * timing and never synchronises (except in the debug mode, as above); it may
+ * be captured into a graph.
+ *   - q must be a uniform grid and the context's form must not be
+ *     SAS_FORM_DIRECT (the direct form needs its grid uploaded):
+ *     SAS_ERR_UNSUPPORTED otherwise.
+ *   - Sizes whose scratch exceeds SAS_NOALLOC_SCRATCH_BYTES give
+ *     SAS_ERR_UNSUPPORTED with the bytes needed; 64 MiB holds a 50,000-atom
+ *     profile of 200 q with 5 types.
+ *   - Every call on one GPU, from any context or thread, shares that GPU's
+ *     array: calls that overlap in time on one GPU (two streams, two threads,
+ *     two contexts) race and give wrong results.  Order them on one stream.
+ *     Each call rewrites every scratch region it reads, so no clearing is
+ *     needed between calls.
+ */
+#define SAS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sas_status sas_debye_profile_noalloc(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                     const float* table, int32_t t, const double* q, int32_t nq, double* I_out,
+                                     void* stream);
+
+/*
  * Batched profiles of S structures that share one table and one q grid (the
  * ensemble use the paper's introduction motivates: many conformations or
  * structures evaluated together).  Atoms of structure s are rows

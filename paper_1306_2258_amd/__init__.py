@@ -32,7 +32,7 @@ from . import _lib
 from ._lib import SasError, check, load
 
 __all__ = [
-    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_batched",
+    "Context", "SasError", "q_grid_check", "debye_profile", "debye_profile_noalloc", "debye_profile_batched",
     "debye_grad", "debye_grad_table",
     "debye_profile_hybrid", "orient_degree",
     "BatchedPlan", "DebyeProfile", "debye_profile_autograd", "default_context",
@@ -207,6 +207,25 @@ def debye_profile(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor
     check(load().sas_debye_profile(ctx.handle, _ptr(coords), _ptr(types), n, _ptr(table), t,
                                    qh.ctypes.data_as(ctypes.c_void_p), nq, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream(coords.device)), "sas_debye_profile")
+    return out
+
+
+def debye_profile_noalloc(coords: torch.Tensor, types: torch.Tensor, table: torch.Tensor, q, *,
+                          ctx: Optional[Context] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """debye_profile through sas_debye_profile_noalloc: no workspace, the
+    library's fixed per-GPU scratch instead (uniform q grids; sizes up to its
+    SAS_NOALLOC_SCRATCH_BYTES).  Pass ``out`` to allocate nothing at all."""
+    _check_inputs(coords, types, table)
+    ctx = ctx or default_context(coords.device)
+    qh = _q_host(q)
+    n, t, nq = coords.shape[0], table.shape[0], len(qh)
+    if table.shape[1] != nq:
+        raise ValueError(f"table has {table.shape[1]} columns for {nq} q values")
+    if out is None:
+        out = torch.empty(nq, dtype=torch.float64, device=coords.device)
+    check(load().sas_debye_profile_noalloc(ctx.handle, _ptr(coords), _ptr(types), n, _ptr(table), t,
+                                           qh.ctypes.data_as(ctypes.c_void_p), nq, _ptr(out),
+                                           _stream(coords.device)), "sas_debye_profile_noalloc")
     return out
 
 

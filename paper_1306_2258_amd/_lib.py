@@ -37,6 +37,7 @@ SIGNATURES = {
     "sas_q_grid_check": (ctypes.c_int, [P, I32, P, P]),
     "sas_debye_workspace_size": (SZ, [P, I64, I32, I32, ctypes.c_int]),
     "sas_debye_profile": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, P, P, SZ, P]),
+    "sas_debye_profile_noalloc": (ctypes.c_int, [P, P, P, I64, P, I32, P, I32, P, P]),
     "sas_debye_workspace_size_batched": (SZ, [P, P, I32, I32, I32]),
     "sas_debye_profile_batched": (ctypes.c_int, [P, P, P, P, I32, P, I32, P, I32, P, P, SZ, P]),
     "sas_plan_create_batched": (ctypes.c_int, [P, P, P, P, I32, P, I32, P, I32, P, P, SZ, P]),

@@ -21,6 +21,14 @@ using sas::DescView;
 using sas::Geometry;
 using sas::StructDesc;
 
+// Scratch memory of sas_debye_profile_noalloc: a fixed array in device memory,
+// one copy per GPU the library runs on, held until the process ends.  In host
+// code this name stands for a host-side shadow, not a device address, so it is
+// never passed to a kernel or a copy: sas_create looks up each device's
+// address once (hipGetSymbolAddress, that device current) and every use goes
+// through that address.
+static __device__ __align__(256) unsigned char scratch[SAS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -85,9 +93,12 @@ struct sas_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_fwd, ev_adj;
   std::vector<hipEvent_t> ev_pool;
   // SAS_DEBUG_VALIDATE: check types and coordinates on the device before
-  // each call (a synchronisation each); four counters on the device
+  // each call (a synchronisation each); four counters on the device,
+  // allocated when the context is created
   bool debug_validate = false;
   unsigned long long* dbg = nullptr;
+  // this device's copy of the allocation-free call's scratch array
+  void* scratch = nullptr;
   // hybrid profiles: a second stream (default priority) for the direct part,
   // which runs beside the orientation average, and the events that fork it
   // from and join it back into the caller's stream
@@ -484,7 +495,7 @@ sas_status debug_validate(sas_ctx* ctx, const float* coords, const int32_t* type
   if (!ctx->debug_validate || n <= 0) return SAS_OK;
   const sas_status cs = refuse_capture(hs, "debug mode (SAS_DEBUG_VALIDATE)");
   if (cs != SAS_OK) return cs;
-  if (!ctx->dbg) SAS_HIP(hipMalloc(reinterpret_cast<void**>(&ctx->dbg), 4 * sizeof(unsigned long long)));
+  if (!ctx->dbg) return fail(SAS_ERR_HIP, "debug counters were not allocated");
   SAS_HIP(hipMemsetAsync(ctx->dbg, 0, 2 * sizeof(unsigned long long), hs));
   SAS_HIP(hipMemsetAsync(ctx->dbg + 2, 0xff, 2 * sizeof(unsigned long long), hs));
   SAS_HIP(sas::launch_validate(coords, types, n, t, ctx->dbg, hs));
@@ -794,6 +805,28 @@ sas_status sas_q_grid_check(const double* q, int32_t nq, double* q0, double* dq)
   return SAS_OK;
 }
 
+namespace {
+
+// Device address of `scratch` per device id, looked up once per device.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;
+
+sas_status scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (static_cast<int>(g_scratch_addr.size()) <= device) g_scratch_addr.resize(device + 1, nullptr);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SAS_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return SAS_OK;
+}
+
+}  // namespace
+
 sas_status sas_create(int device, sas_ctx** out) {
   if (!out) return fail(SAS_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
@@ -814,6 +847,21 @@ sas_status sas_create(int device, sas_ctx** out) {
   c->debug_validate = dv && dv[0] && std::strcmp(dv, "0") != 0;
   const char* tl = std::getenv("SAS_TUNE_LOG");
   c->tune_log = tl && tl[0] && std::strcmp(tl, "0") != 0;
+  {
+    DeviceGuard g(device);
+    if (!g.ok) {
+      delete c;
+      return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", device);
+    }
+    sas_status st = scratch_address(device, &c->scratch);
+    if (st == SAS_OK && c->debug_validate &&
+        hipMalloc(reinterpret_cast<void**>(&c->dbg), 4 * sizeof(unsigned long long)) != hipSuccess)
+      st = fail(SAS_ERR_OUT_OF_MEMORY, "debug counters: hipMalloc failed");
+    if (st != SAS_OK) {
+      delete c;
+      return st;
+    }
+  }
   *out = c;
   return SAS_OK;
 }
@@ -978,6 +1026,41 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
   st = stage_upload(ctx, workspace, L, upload_image(sc, L, grid), hs);
   if (st != SAS_OK) return st;
   st = enqueue_forward(ctx, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, workspace, hs);
+  if (st == SAS_OK) note_last(ctx, sc);
+  return st;
+}
+
+sas_status sas_debye_profile_noalloc(sas_ctx* ctx, const float* coords, const int32_t* types, int64_t n,
+                                     const float* table, int32_t t, const double* q, int32_t nq, double* I_out,
+                                     void* stream) {
+  if (!ctx) return fail(SAS_ERR_INVALID_ARG, "ctx is NULL");
+  sas_status st = check_sizes(n, t, nq);
+  if (st != SAS_OK) return st;
+  if (n > 0 && (!coords || !types)) return fail(SAS_ERR_INVALID_ARG, "coords/types is NULL");
+  if (!table || !I_out) return fail(SAS_ERR_INVALID_ARG, "table/I_out is NULL");
+  QGrid grid;
+  st = classify_q(q, nq, &grid);
+  if (st != SAS_OK) return st;
+  // the direct form reads its q grid from device memory, which would need an
+  // upload through the context's pinned staging
+  if (!grid.uniform || ctx->force_direct)
+    return fail(SAS_ERR_UNSUPPORTED, "the allocation-free call takes uniform q grids on the recurrence form only");
+  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, false, use_per_atom(ctx, t, n));
+  const Layout L = make_layout(sc, t, nq);
+  if (L.upload_bytes != 0) return fail(SAS_ERR_UNSUPPORTED, "this call would upload host data");
+  if (L.total > SAS_NOALLOC_SCRATCH_BYTES)
+    return fail(SAS_ERR_UNSUPPORTED, "n = %lld, t = %d, nq = %d needs %zu bytes of scratch; the allocation-free "
+                "call has %zu (use sas_debye_profile with a workspace)", (long long)n, t, nq, L.total,
+                (size_t)SAS_NOALLOC_SCRATCH_BYTES);
+  if (!ctx->scratch) return fail(SAS_ERR_HIP, "no scratch address for device %d", ctx->device);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(SAS_ERR_HIP, "hipSetDevice(%d) failed", ctx->device);
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  st = debug_validate(ctx, coords, types, n, t, hs);
+  if (st != SAS_OK) return st;
+  // no kernel timing (its events are created on demand); every kernel of the
+  // path writes the scratch regions it reads, so nothing is cleared first
+  st = enqueue_forward(nullptr, sc, L, coords, types, table, t, nq, grid.q0, grid.dq, I_out, ctx->scratch, hs);
   if (st == SAS_OK) note_last(ctx, sc);
   return st;
 }
