@@ -224,7 +224,8 @@ def main(argv=None):
     kern_ms = kt["forward_ms"] / max(kt["forward_launches"], 1)
     achieved = EXEC_FLOPS_PER_PAIR_Q * work / (kern_ms / 1e3) / 1e12
     bj, qc = ctx.variant()
-    kname = f"k_forward<{qc}, {bj}>"
+    launch = ctx.launch()
+    kname = f"k_forward_persist<{qc}, {bj}>" if launch == "persistent" else f"k_forward<{qc}, {bj}>"
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe)
         src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
@@ -250,7 +251,7 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "dna_rod_50k", "atoms": m.n, "nq": len(m.q), "q_range": [0.0, 1.0], "types": 5,
-                   "pair_q_per_step": work, "variant": {"bj": bj, "qc": qc}},
+                   "pair_q_per_step": work, "variant": {"bj": bj, "qc": qc, "launch": launch}},
         "ms_per_step_median": float(np.median(per_step)) if per_step else None,
         "ms_per_step_min": float(np.min(per_step)) if per_step else None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -357,7 +358,19 @@ def bench_batched(sd, W, torch, dev):
     try:
         plan = sd.BatchedPlan(coords, types, e.offsets, table, e.q, ctx=ctx)
         res["ms_plan_replay"] = _time(plan.execute, torch)
+        bj, qc = ctx.variant()
+        res["plan_variant"] = {"bj": bj, "qc": qc, "launch": ctx.launch()}
         plan.close()
+        # the tuned shape with each launch of the pair kernel forced
+        ab = {}
+        for launch in ("grid", "persistent"):
+            actx = sd.Context(0)
+            actx.set_variant(bj, qc)
+            actx.set_form(launch)
+            p2 = sd.BatchedPlan(coords, types, e.offsets, table, e.q, ctx=actx)
+            ab[f"ms_{launch}"] = _time(p2.execute, torch)
+            p2.close()
+        res["plan_launch_ab"] = ab
     except sd.SasError as exc:
         res["plan"] = str(exc)[:120]
     views = [(coords[int(a):int(b)], types[int(a):int(b)]) for a, b in zip(e.offsets[:-1], e.offsets[1:])]
