@@ -12,6 +12,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "sas_device.hpp"
 #include "sas_forward.hpp"
 #include "sas_kernels.hpp"
@@ -269,20 +271,26 @@ __global__ __launch_bounds__(kWave, forward_waves(QC, BJ, false)) void k_forward
   }
 }
 
-// Work-groups of k_forward_persist<QC, BJ> resident on the whole GPU (the
-// occupancy query, once per template and process).
+// Work-groups of k_forward_persist<QC, BJ> resident on the current GPU (the
+// occupancy query, cached per template and device).
 template <int QC, int BJ>
 int64_t persist_slots() {
-  static int64_t slots = -1;
-  if (slots < 0) {
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_persist<QC, BJ>, kWave, 0) != hipSuccess ||
-        per_cu <= 0)
-      return 0;
-    slots = static_cast<int64_t>(per_cu) * prop.multiProcessorCount;
+  constexpr int kMaxDev = 64;
+  static std::atomic<int64_t> cache[kMaxDev];  // 0: not queried yet
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev < kMaxDev) {
+    const int64_t c = cache[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
   }
+  int per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_forward_persist<QC, BJ>, kWave, 0) != hipSuccess ||
+      per_cu <= 0)
+    return 0;
+  const int64_t slots = static_cast<int64_t>(per_cu) * prop.multiProcessorCount;
+  if (dev < kMaxDev) cache[dev].store(slots, std::memory_order_relaxed);
   return slots;
 }
 

@@ -376,6 +376,9 @@ def test_persistent_launch_matches_grid(sd, nq):
     assert np.array_equal(a, b)
     d = sd.debye_profile_batched(c, t, off, tab, mols[0].q, ctx=auto_ctx).cpu().numpy()
     assert auto_ctx.launch() == "grid" and np.array_equal(a, d)
+    with pytest.raises(sd.SasError) as e:
+        auto_ctx.set_form("persistent+grid")
+    assert e.value.status == 1
 
 
 def test_plan_reuses_tuned_shape(sd):
