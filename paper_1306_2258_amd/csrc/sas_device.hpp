@@ -144,8 +144,8 @@ struct SinCosF {
 };
 
 __device__ __forceinline__ SinCosF sincos_qr(double q, double rp) {
-  const double s = fma(q, rp, kRoundMagic);
-  const double k = s - kRoundMagic;
+  const double s = fma_vvs(q, rp, kRoundMagic);
+  const double k = add_vs(s, -kRoundMagic);
   const float x = static_cast<float>(fma(q, rp, -k));
   const unsigned flip = static_cast<unsigned>(__double2loint(s)) << 31;
   const float xs = __uint_as_float(__float_as_uint(x) + flip);
@@ -165,9 +165,16 @@ __device__ __forceinline__ SinCosF sincos_qr(double q, double rp) {
   return r;
 }
 
+// acc + a * b written in place (v_fmac_f32), so that the accumulators of the
+// direct forms' two sine evaluations keep their registers.
+__device__ __forceinline__ float fmac_inplace(float a, float b, float acc) {
+  asm("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(a), "v"(b));
+  return acc;
+}
+
 __device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
-  const double s = fma(q, rp, kRoundMagic);
-  const double k = s - kRoundMagic;
+  const double s = fma_vvs(q, rp, kRoundMagic);
+  const double k = add_vs(s, -kRoundMagic);
   const float x = static_cast<float>(fma(q, rp, -k));
   const unsigned lo = static_cast<unsigned>(__double2loint(s));
   const float xs = __uint_as_float(__float_as_uint(x) + (lo << 31));
@@ -176,7 +183,80 @@ __device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float 
   p = fmaf(p, y, kSinPi2);
   p = fmaf(p, y, kSinPi1);
   p = fmaf(p, y, kSinPi0);
-  return fmaf(xs * w, p, acc);
+  return fmac_inplace(xs * w, p, acc);
+}
+
+// Direct form, one-FMA reduction, for four q values at a time:
+// acc[g] + sin(q[g] r) w[g] from rp = r / pi, for 1/4 <= t = q rp < 2^19.
+// One FMA adds 1.5 * 2^21 + 1/2, which puts the sum in [2^21, 2^22), where its
+// last bit is worth 2^-31: it holds t + 1/2 rounded to a multiple of 2^-31
+// (to nearest), and its low word read as a signed integer is v 2^31 with
+// v = t + 1/2 (mod 2), v in [-1, 1).  Then sin(pi t) = -cos(pi v) =
+// -cos(pi |v|) = sin(pi b) with b = |v| - 1/2 in [-1/2, 1/2]: one conversion
+// and one FMA give b, with no sign to apply, and sin(pi b) = b P(b^2) as in
+// the exact form.  The conversion rounds |v| to FP32, an absolute error of at
+// most 2^-25 in b, so the relative accuracy of the smallest sines holds for
+// t >= 1/4 (smaller t take the exact form).  On gfx950 FP32 additions,
+// products and FMAs whose operands are VGPRs, literals or inline constants
+// issue at twice the rate of conversions, FP64 operations and FP32
+// operations that read an SGPR; so the scale 2^-31 comes in a VGPR
+// (`scale`), and the four values' steps are issued stage by stage (one FP64
+// FMA and one conversion, then eight full-rate operations each), which lets
+// their latencies overlap.
+constexpr double kHalfMagic = 0x1.8p+21 + 0.5;
+constexpr double kFracMinT = 0x1p-2, kFracMaxT = 0x1p+19;
+template <bool PER_Q>
+__device__ __forceinline__ void sin_qr_acc4_frac(const double* q, double rp, float w, const float* wq, float scale,
+                                                 float* acc) {
+  double s[4];
+  float b[4], y[4], p[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) s[g] = fma_vvs(q[g], rp, kHalfMagic);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(__double2loint(s[g]));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_fma_f32 %0, |%1|, %2, -0.5" : "=v"(b[g]) : "v"(b[g]), "v"(scale));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) y[g] = b[g] * b[g];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) p[g] = fmaf(y[g], kSinPi4, kSinPi3);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi2);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi1);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi0);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] *= PER_Q ? w * wq[g] : w;
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = fmac_inplace(b[g], p[g], acc[g]);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// The squared distances r^2 in [r2_lo, r2_hi) for which sin_qr_acc4_frac
+// holds its accuracy at every q in [q_lo, q_hi] (t = q r / pi from 1/4 at
+// q_lo to 2^19 at q_hi; q_lo = 0 gives an empty range).  Testing r^2 costs a
+// pair two FP64 comparisons instead of two products and two comparisons.
+struct FracRange {
+  double r2_lo, r2_hi;
+};
+__device__ __forceinline__ FracRange frac_range(double q_lo, double q_hi) {
+  constexpr double kPi = 0x1.921fb54442d18p+1;
+  const double a = kFracMinT * kPi / q_lo, b = kFracMaxT * kPi / q_hi;
+  return {a * a, b * b};
+}
+// Whether a pair (w = 0: it adds nothing either way) admits sin_qr_acc4_frac.
+__device__ __forceinline__ bool frac_reduction_ok(const FracRange& fr, double r2, float w) {
+  return w == 0.f || (r2 >= fr.r2_lo && r2 < fr.r2_hi);
 }
 
 }  // namespace sas

@@ -72,8 +72,10 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
   // direct form: this chunk's q values (0 past the end of the grid)
   __shared__ double qv[DIRECT ? QC : 1];
+  FracRange frange{0.0, 0.0};  // from the chunk's smallest and largest q (the grid ascends)
   if constexpr (DIRECT) {
     for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
+    frange = frac_range(a.qdev[m0], a.qdev[m0 + nqc - 1]);
   }
 
 #pragma unroll 1
@@ -118,18 +120,46 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
       for (int m = 0; m < QC; ++m) acc[m] = 0.f;
       if constexpr (DIRECT) {
         // arbitrary q grid: sin(q_m r)/r evaluated for every q, one pair per
-        // iteration (the q steps are independent of each other)
-#pragma unroll 1
-        for (int jl = sa; jl < sb; ++jl) {
+        // iteration (the q steps are independent of each other).  A pair whose
+        // lanes all admit the one-FMA reduction over the chunk is summed at
+        // once; the others (near-coincident atoms at the chunk's smallest q)
+        // are listed and summed after the segment with the exact reduction, so
+        // that each loop has one accumulating path (two paths in one loop make
+        // the compiler copy the accumulators after every pair).
+        __shared__ int slow[DIRECT ? BJ : 1];
+        int nslow = 0;
+        float kScale31 = 0x1p-31f;  // (held in a VGPR: see sin_qr_acc4_frac)
+        asm volatile("" : "+v"(kScale31));
+        auto pair_setup = [&](int jl, double& rp, double& r2, float& w) {
           // (the q values are re-read from LDS for every pair rather than
           // held in 64 VGPRs: four waves per SIMD instead of three)
           asm volatile("" ::: "memory");
           const double4 pj = sj[jl - j0];
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
+          r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
           const double ir = rsqrt_f64(r2);
-          const double rp = r2 * ir * kOneOverPi;
-          const float w = (on && jl > i) ? static_cast<float>(ir) : 0.f;
+          rp = r2 * ir * kOneOverPi;
+          w = (on && jl > i) ? static_cast<float>(ir) : 0.f;
+        };
+#pragma unroll 1
+        for (int jl = sa; jl < sb; ++jl) {
+          double rp, r2;
+          float w;
+          pair_setup(jl, rp, r2, w);
+          if (__all(frac_reduction_ok(frange, r2, w))) {
+            static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+#pragma unroll
+            for (int m = 0; m < QC; m += 4) sin_qr_acc4_frac<false>(qv + m, rp, w, nullptr, kScale31, acc + m);
+          } else {
+            slow[nslow] = jl;  // (every lane stores the same value)
+            ++nslow;
+          }
+        }
+#pragma unroll 1
+        for (int k = 0; k < nslow; ++k) {
+          double rp, r2;
+          float w;
+          pair_setup(slow[k], rp, r2, w);
 #pragma unroll
           for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w, acc[m]);
         }

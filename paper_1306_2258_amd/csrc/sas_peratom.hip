@@ -122,8 +122,10 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
   const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
+  FracRange frange{0.0, 0.0};  // from the chunk's smallest and largest q (the grid ascends)
   if constexpr (DIRECT) {
     for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
+    frange = frac_range(a.qdev[m0], a.qdev[m0 + nqc - 1]);
   }
 
   const int bj = a.geo.bj;
@@ -168,15 +170,43 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
       }
       __syncthreads();
       if constexpr (DIRECT) {
-#pragma unroll 1
-        for (int jl = u0; jl < u0 + ns; ++jl) {
+        // the one-FMA reduction for pairs whose lanes all admit it over the
+        // chunk; the rest are listed and summed after the run with the exact
+        // reduction (one accumulating path per loop, as in the type form)
+        __shared__ int slow[DIRECT ? kPaSub : 1];
+        int nslow = 0;
+        float kScale31 = 0x1p-31f;  // (held in a VGPR: see sin_qr_acc4_frac)
+        asm volatile("" : "+v"(kScale31));
+        auto pair_setup = [&](int jl, double& rp, double& r2, float& w) {
           asm volatile("" ::: "memory");
           const double4 pj = sj[jl - u0];
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-          const double r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
+          r2 = fmax(fma(dz, dz, fma(dy, dy, dx * dx)), 1e-60);
           const double ir = rsqrt_f64(r2);
-          const double rp = r2 * ir * kOneOverPi;
-          const float w = (vi && (ROWS ? jl != i : jl > i)) ? static_cast<float>(ir) : 0.f;
+          rp = r2 * ir * kOneOverPi;
+          w = (vi && (ROWS ? jl != i : jl > i)) ? static_cast<float>(ir) : 0.f;
+        };
+#pragma unroll 1
+        for (int jl = u0; jl < u0 + ns; ++jl) {
+          double rp, r2;
+          float w;
+          pair_setup(jl, rp, r2, w);
+          if (__all(frac_reduction_ok(frange, r2, w))) {
+            const float* fb = fj[jl - u0];
+            static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+#pragma unroll
+            for (int m = 0; m < QC; m += 4) sin_qr_acc4_frac<true>(qv + m, rp, w, fb + m, kScale31, acc + m);
+          } else {
+            slow[nslow] = jl;  // (every lane stores the same value)
+            ++nslow;
+          }
+        }
+#pragma unroll 1
+        for (int k = 0; k < nslow; ++k) {
+          const int jl = slow[k];
+          double rp, r2;
+          float w;
+          pair_setup(jl, rp, r2, w);
           const float* fb = fj[jl - u0];
 #pragma unroll
           for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w * fb[m], acc[m]);

@@ -161,6 +161,39 @@ def test_nonuniform_coincident_and_large_q(sd):
     check(sd, m)
 
 
+# The direct form reduces t = q r / pi by one FP64 FMA when every lane's pair
+# has t >= 1/4 at its q chunk's smallest q, and exactly otherwise.
+@pytest.mark.parametrize("t_lo", [0.05, 0.2499, 0.2501, 0.3, 4.0, 3000.0])
+def test_direct_reduction_switch_pair(sd, t_lo):
+    """One pair whose t at the chunk's first q sits on either side of 1/4:
+    the profile of each chunk against the oracle's, tighter than the 1e-6 bar."""
+    say(f"direct form, one pair at t = {t_lo} for the first chunk's smallest q")
+    q = W.log_grid(0.01, 1.0, 64)  # two chunks of 32: smallest q 0.01 and about 0.1
+    r = t_lo * np.pi / q[0]
+    coords = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]], dtype=np.float32)
+    types = np.zeros(2, dtype=np.int32)
+    m = W.Molecule("pair", coords, types, W.gaussian_table([6.0], [0.5], q), q)
+    got = gpu_profile(sd, m)
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    err = rel_err(got, ref)
+    assert err.max() <= 3e-7, f"t_lo={t_lo}: {err.max():.3e} at q[{err.argmax()}]"
+
+
+def test_direct_reduction_switch_mixed(sd):
+    """Atoms along a 400 A line: within a wave some pairs are below the
+    one-FMA reduction's range at the low-q chunks and some above, so waves
+    take either reduction and the listed pairs are summed after the others."""
+    say("direct form, pairs on both sides of the one-FMA reduction's range")
+    q = W.log_grid(0.01, 1.0, 96)
+    rng = np.random.default_rng(801)
+    x = np.sort(rng.uniform(0.0, 400.0, 900))
+    pts = np.stack([x, rng.normal(0.0, 3.0, 900), rng.normal(0.0, 3.0, 900)], axis=1).astype(np.float32)
+    types = rng.integers(0, 3, size=900).astype(np.int32)
+    m = W.Molecule("line", pts, types, W.gaussian_table([1.0, 6.0, 8.0], [0.5, 0.8, 1.1], q), q)
+    e = check(sd, m)
+    print(f"max rel err {e:.3e}")
+
+
 @pytest.mark.parametrize("bj", [64, 128, 256, 512])
 def test_nonuniform_variants_and_determinism(sd, bj):
     say(f"non-uniform grid, forced bj={bj}, two calls bitwise equal")
