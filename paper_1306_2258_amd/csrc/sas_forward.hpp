@@ -99,6 +99,38 @@ __device__ __forceinline__ void rec_step2(float& acc, float& za, float& zb, floa
     SAS_STEP2_ASM(88, 89, 90, 91, 92, 93, 94, 95);
 }
 #undef SAS_STEP2_ASM
+
+// Four consecutive q steps (m even: even, odd, even, odd) of the same two
+// pairs in one asm block.  The compiler follows each inline asm statement
+// with an s_nop; in the two-wave kernels (chunks above 128 q) one block per
+// four steps instead of one per step made the rod's pair kernel 3.4% faster
+// (the three-wave kernels, where the other waves hide the nops, were 1-2%
+// slower with it and keep one step per block).
+#define SAS_STEP8_ASM(R0, R1, R2, R3, R4, R5, R6, R7)                                                   \
+  asm("v_add_f32 %0, %0, %4\n v_add_f32 %0, %0, %5\n v_add_f32 %4, %4, %6\n"                          \
+      "v_add_f32 %5, %5, %7\n v_fmac_f32 %6, %10, %4\n v_fmac_f32 %7, %11, %5\n"                      \
+      "v_fmac_f32 %1, %8, %4\n v_fmac_f32 %1, %9, %5\n v_add_f32 %4, %4, %6\n"                        \
+      "v_add_f32 %5, %5, %7\n v_fmac_f32 %6, %10, %4\n v_fmac_f32 %7, %11, %5\n"                      \
+      "v_add_f32 %2, %2, %4\n v_add_f32 %2, %2, %5\n v_add_f32 %4, %4, %6\n"                          \
+      "v_add_f32 %5, %5, %7\n v_fmac_f32 %6, %10, %4\n v_fmac_f32 %7, %11, %5\n"                      \
+      "v_fmac_f32 %3, %8, %4\n v_fmac_f32 %3, %9, %5\n v_add_f32 %4, %4, %6\n"                        \
+      "v_add_f32 %5, %5, %7\n v_fmac_f32 %6, %10, %4\n v_fmac_f32 %7, %11, %5"                        \
+      : "+v"(acc0), "+v"(acc1), "+v"(acc2), "+v"(acc3), "+" SAS_PIN(R0)(za), "+" SAS_PIN(R1)(zb),      \
+        "+" SAS_PIN(R4)(da), "+" SAS_PIN(R5)(db)                                                      \
+      : SAS_PIN(R2)(sga), SAS_PIN(R3)(sgb), SAS_PIN(R6)(nla), SAS_PIN(R7)(nlb))
+
+template <int BASE>
+__device__ __forceinline__ void rec_step8(float& acc0, float& acc1, float& acc2, float& acc3, float& za, float& zb,
+                                          float& da, float& db, float sga, float sgb, float nla, float nlb) {
+  static_assert(BASE == 248 || BASE == 160 || BASE == 88, "pinned register base");
+  if constexpr (BASE == 248)
+    SAS_STEP8_ASM(248, 249, 250, 251, 252, 253, 254, 255);
+  else if constexpr (BASE == 160)
+    SAS_STEP8_ASM(160, 161, 162, 163, 164, 165, 166, 167);
+  else
+    SAS_STEP8_ASM(88, 89, 90, 91, 92, 93, 94, 95);
+}
+#undef SAS_STEP8_ASM
 #undef SAS_PIN
 
 // Register base for rec_step2 in a kernel of `waves` waves per SIMD (512

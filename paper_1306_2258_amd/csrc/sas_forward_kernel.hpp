@@ -204,8 +204,13 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
         // operands from one bank; the negated lambdas are plain register
         // operands, so the FMAs keep the 32-bit v_fmac encoding)
         constexpr int kPin = pin_base(QC > 128 ? 2 : 3, QC <= 32);
+        // (four steps per asm block in the two-wave kernels: see rec_step8)
+        constexpr int M4 = QC > 128 ? QC / 4 * 4 : 0;
 #pragma unroll
-        for (int m = 0; m < QC; ++m) {
+        for (int m = 0; m < M4; m += 4)
+          rec_step8<kPin>(acc[m], acc[m + 1], acc[m + 2], acc[m + 3], za, zb, da, db, A.sg, B.sg, A.nlam, B.nlam);
+#pragma unroll
+        for (int m = M4; m < QC; ++m) {
           if (m & 1)
             rec_step2<kPin, true>(acc[m], za, zb, da, db, A.sg, B.sg, A.nlam, B.nlam);
           else
