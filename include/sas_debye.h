@@ -153,9 +153,13 @@ sas_status sas_debye_profile(sas_ctx* ctx, const float* coords, const int32_t* t
  *   - q must be a uniform grid and the context's form must not be
  *     SAS_FORM_DIRECT (the direct form needs its grid uploaded):
  *     SAS_ERR_UNSUPPORTED otherwise.
- *   - Sizes whose scratch exceeds SAS_NOALLOC_SCRATCH_BYTES give
- *     SAS_ERR_UNSUPPORTED with the bytes needed; 64 MiB holds a 50,000-atom
- *     profile of 200 q with 5 types.
+ *   - When the automatic tile shape's strip rows do not fit the array (and
+ *     no shape was forced with sas_set_variant), the call takes the shortest
+ *     longer J block whose rows fit, up to 512 atoms; its sums then run in
+ *     another order than sas_debye_profile's, to the same accuracy.  Sizes
+ *     that fit no shape give SAS_ERR_UNSUPPORTED with the bytes needed;
+ *     64 MiB holds a 50,000-atom profile of 200 q with 5 types (J blocks of
+ *     512 atoms).
  *   - Every call on one GPU, from any context or thread, shares that GPU's
  *     array: calls that overlap in time on one GPU (two streams, two threads,
  *     two contexts) race and give wrong results.  Order them on one stream.

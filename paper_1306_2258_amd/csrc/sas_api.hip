@@ -218,12 +218,14 @@ bool use_per_atom(const sas_ctx* ctx, int32_t T, int64_t max_n) {
   return T >= 64 && max_n < 16LL * T;
 }
 
-// J-block size by the largest structure (measured on MI355X: 512 atoms for
-// the 50,000-atom rod, 256 for 20,000 atoms, 128 for 10,000): long enough to
-// amortise the per-segment lane reduction, short enough to leave many strips.
+// J-block size by the largest structure (measured on MI355X with the current
+// pair kernels: 256 atoms for the 50,000-atom rod, 128 for the 20,000-atom
+// lattice and for 10,000 atoms; same-box A/B of whole calls against 512 and
+// 256, 0.7% faster each): long enough to amortise the per-segment lane
+// reduction, short enough to leave many strips.
 int32_t default_bj(int64_t max_n) {
-  if (max_n >= 40000) return 512;
-  if (max_n >= 15000) return 256;
+  if (max_n >= 40000) return 256;
+  if (max_n >= 15000) return 128;
   if (max_n >= 2048) return 128;
   return 64;
 }
@@ -1045,8 +1047,15 @@ sas_status sas_debye_profile_noalloc(sas_ctx* ctx, const float* coords, const in
   // upload through the context's pinned staging
   if (!grid.uniform || ctx->force_direct)
     return fail(SAS_ERR_UNSUPPORTED, "the allocation-free call takes uniform q grids on the recurrence form only");
-  const Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, false, use_per_atom(ctx, t, n));
-  const Layout L = make_layout(sc, t, nq);
+  const bool pa = use_per_atom(ctx, t, n);
+  Schedule sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, 0, 0, false, pa);
+  Layout L = make_layout(sc, t, nq);
+  // unless the caller forced a shape: when the strip rows do not fit, the
+  // shortest longer J block whose rows do (each doubling halves the strips)
+  for (int32_t bj = sc.geo.bj * 2; L.total > SAS_NOALLOC_SCRATCH_BYTES && ctx->force_bj == 0 && bj <= 512; bj *= 2) {
+    sc = make_schedule(ctx, std::vector<int64_t>{n}, t, nq, bj, 0, false, pa);
+    L = make_layout(sc, t, nq);
+  }
   if (L.upload_bytes != 0) return fail(SAS_ERR_UNSUPPORTED, "this call would upload host data");
   if (L.total > SAS_NOALLOC_SCRATCH_BYTES)
     return fail(SAS_ERR_UNSUPPORTED, "n = %lld, t = %d, nq = %d needs %zu bytes of scratch; the allocation-free "

@@ -82,9 +82,15 @@ def test_two_calls_match_workspace_call_and_oracle(env):
         want = torch.full((len(m.q),), float("nan"), dtype=torch.float64, device="cuda")
         st = call_noalloc(lib, ctx, c, t, tab, m.q, got, stream)
         assert st == 0, lib.sas_last_error()
-        st, ws = call_workspace(lib, ctx, c, t, tab, m.q, want, stream)
+        # the workspace call on the tile shape the allocation-free call used
+        # (it may take a longer J block to fit its scratch): bitwise equal
+        shape = ctx.variant()
+        ctx2 = sd.Context(0)
+        ctx2.set_variant(shape[0], shape[1])
+        st, ws = call_workspace(lib, ctx2, c, t, tab, m.q, want, stream)
         assert st == 0, lib.sas_last_error()
         torch.cuda.synchronize()
+        assert ctx2.variant()[:2] == shape[:2]
         assert torch.equal(got, want), f"{m.name}: allocation-free result differs from the workspace call"
         q, I, _ = load(golden)
         assert np.array_equal(q, m.q)
@@ -111,7 +117,10 @@ def test_second_call_smaller_than_first(env):
         got = torch.full((len(m.q),), float("nan"), dtype=torch.float64, device="cuda")
         want = torch.full((len(m.q),), float("nan"), dtype=torch.float64, device="cuda")
         assert call_noalloc(lib, ctx, c, t, tab, m.q, got, stream) == 0, lib.sas_last_error()
-        st, ws = call_workspace(lib, ctx, c, t, tab, m.q, want, stream)
+        shape = ctx.variant()
+        ctx2 = sd.Context(0)
+        ctx2.set_variant(shape[0], shape[1])
+        st, ws = call_workspace(lib, ctx2, c, t, tab, m.q, want, stream)
         assert st == 0, lib.sas_last_error()
         torch.cuda.synchronize()
         assert torch.equal(got, want), m.name
@@ -140,6 +149,15 @@ def test_refusals(env):
     assert call_noalloc(lib, ctx, c, t, tab, q, out, stream) == 3
     msg = lib.sas_last_error().decode()
     assert "bytes of scratch" in msg and str(64 << 20) in msg, msg
+    # a forced tile shape is kept: 50,000 atoms fit with J blocks of 512
+    # atoms (the automatic choice when the default's rows do not fit), not
+    # with a forced 128
+    n5 = 50000
+    c5 = torch.zeros((n5, 3), dtype=torch.float32, device="cuda")
+    t5 = torch.zeros(n5, dtype=torch.int32, device="cuda")
+    ctx.set_variant(128, 0)
+    assert call_noalloc(lib, ctx, c5, t5, tab, q, out, stream) == 3
+    ctx.set_variant(0, 0)
     m = W.random_molecule(7102, 300, 0, q=W.log_grid(1e-3, 0.8, 40), extent=15.0)
     c2, t2, tab2 = to_dev(m)
     out2 = torch.full((40,), 7.0, dtype=torch.float64, device="cuda")
