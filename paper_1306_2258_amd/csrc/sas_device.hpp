@@ -202,11 +202,12 @@ __device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float 
 // operations that read an SGPR; so the scale 2^-31 comes in a VGPR
 // (`scale`), and the four values' steps are issued stage by stage (one FP64
 // FMA and one conversion, then eight full-rate operations each), which lets
-// their latencies overlap.
+// their latencies overlap.  The q values come by value: the callers load the
+// next group's from LDS before this group's steps.
 constexpr double kHalfMagic = 0x1.8p+21 + 0.5;
 constexpr double kFracMinT = 0x1p-2, kFracMaxT = 0x1p+19;
 template <bool PER_Q>
-__device__ __forceinline__ void sin_qr_acc4_frac(const double* q, double rp, float w, const float* wq, float scale,
+__device__ __forceinline__ void sin_qr_acc4_frac(const double (&q)[4], double rp, float w, const float* wq, float scale,
                                                  float* acc) {
   double s[4];
   float b[4], y[4], p[4];

@@ -148,8 +148,17 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
           pair_setup(jl, rp, r2, w);
           if (__all(frac_reduction_ok(frange, r2, w))) {
             static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+            // (each group's q values loaded before the previous group's steps)
+            double qn[4] = {qv[0], qv[1], qv[2], qv[3]};
 #pragma unroll
-            for (int m = 0; m < QC; m += 4) sin_qr_acc4_frac<false>(qv + m, rp, w, nullptr, kScale31, acc + m);
+            for (int m = 0; m < QC; m += 4) {
+              const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
+              if (m + 4 < QC) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) qn[k] = qv[m + 4 + k];
+              }
+              sin_qr_acc4_frac<false>(qc, rp, w, nullptr, kScale31, acc + m);
+            }
           } else {
             slow[nslow] = jl;  // (every lane stores the same value)
             ++nslow;

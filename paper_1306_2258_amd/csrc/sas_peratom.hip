@@ -194,8 +194,17 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           if (__all(frac_reduction_ok(frange, r2, w))) {
             const float* fb = fj[jl - u0];
             static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+            // (each group's q values loaded before the previous group's steps)
+            double qn[4] = {qv[0], qv[1], qv[2], qv[3]};
 #pragma unroll
-            for (int m = 0; m < QC; m += 4) sin_qr_acc4_frac<true>(qv + m, rp, w, fb + m, kScale31, acc + m);
+            for (int m = 0; m < QC; m += 4) {
+              const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
+              if (m + 4 < QC) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) qn[k] = qv[m + 4 + k];
+              }
+              sin_qr_acc4_frac<true>(qc, rp, w, fb + m, kScale31, acc + m);
+            }
           } else {
             slow[nslow] = jl;  // (every lane stores the same value)
             ++nslow;
