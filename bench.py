@@ -68,20 +68,31 @@ KERNEL_HEADER = os.path.join(ROOT, "paper_1306_2258_amd", "csrc", "sas_kernels.h
 KERNEL_HEADER_PARTS = ("kWave", "StructDesc", "DescView", "Geometry", "ForwardArgs")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and with whitespace collapsed: what
+    the compiler sees (the kernel sources hold no comment markers inside
+    string literals)."""
+    import re
+
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     import hashlib
     import re
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            h.update(_code_only(fh.read()).encode())
     with open(KERNEL_HEADER) as fh:
         text = fh.read()
     for name in KERNEL_HEADER_PARTS:
         m = (re.search(r"constexpr int " + name + r" = [^;]*;", text) or
              re.search(r"struct " + name + r" \{.*?\n\};", text, re.S))
-        h.update((m.group(0) if m else name + " missing").encode())
+        h.update(_code_only(m.group(0) if m else name + " missing").encode())
     return h.hexdigest()[:16]
 
 

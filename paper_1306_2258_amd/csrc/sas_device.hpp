@@ -187,7 +187,8 @@ __device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float 
 }
 
 // Direct form, one-FMA reduction, for four q values at a time:
-// acc[g] + sin(q[g] r) w[g] from rp = r / pi, for 1/4 <= t = q rp < 2^19.
+// acc[g] + w_g sin(q[g] r) from rp = r / pi, for 1/4 <= t = q rp < 2^19,
+// with w_g = w (w wq[g] with PER_Q: the per-atom form's row factors).
 // One FMA adds 1.5 * 2^21 + 1/2, which puts the sum in [2^21, 2^22), where its
 // last bit is worth 2^-31: it holds t + 1/2 rounded to a multiple of 2^-31
 // (to nearest), and its low word read as a signed integer is v 2^31 with

@@ -132,7 +132,8 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
         asm volatile("" : "+v"(kScale31));
         auto pair_setup = [&](int jl, double& rp, double& r2, float& w) {
           // (the q values are re-read from LDS for every pair rather than
-          // held in 64 VGPRs: four waves per SIMD instead of three)
+          // held in 64 VGPRs, which would leave three waves per SIMD instead
+          // of five)
           asm volatile("" ::: "memory");
           const double4 pj = sj[jl - j0];
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
