@@ -546,31 +546,38 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
   outi[3 * lane + 2] = gz;
 }
 
-// One thread per (sorted) atom: the i-side rows of its own row of strips and
-// the j-side rows of every strip that holds its J block, in a fixed order;
-// the sum is written to the caller's row perm[a].
-__global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks, const int32_t* __restrict__ perm,
-                                                     double* __restrict__ grad_out) {
+// The i-side rows of each (sorted) atom's own row of strips and the j-side
+// rows of every strip that holds its J block, summed in FP64; the sum is
+// written to the caller's row perm[a].  A work-group takes 32 atoms and splits
+// each atom's strips among 8 parts (part k takes every 8th strip from the
+// k-th), the 32 threads of a part reading 32 consecutive atoms' rows; the 8
+// partial sums are then added in part order.  (One thread per atom walking
+// all its strips kept most CUs idle: 115 us for 20,000 atoms.)
+constexpr int kGradParts = 8, kGradAtoms = 32;
+__global__ __launch_bounds__(kGradParts * kGradAtoms) void k_grad_reduce(AdjArgs a, int32_t nchunks,
+                                                                        const int32_t* __restrict__ perm,
+                                                                        double* __restrict__ grad_out) {
+  __shared__ double red[kGradParts][kGradAtoms][3];
   const StructDesc d = a.sd.get(0);
-  const int64_t at = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (at >= d.n) return;
+  const int part = threadIdx.x / kGradAtoms, al = threadIdx.x % kGradAtoms;
+  const int64_t at = static_cast<int64_t>(blockIdx.x) * kGradAtoms + al;
   const int64_t n = d.n, c = a.geo.c, g = a.geo.g, bj = a.geo.bj, ib = a.geo.ib;
-  const int64_t nI = ceil_div(n, ib), nJ = ceil_div(n, bj);
-  const int64_t I = at / ib, lane = at % ib, J = at / bj;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  if (n >= 2) {
+  if (at < n && n >= 2) {
+    const int64_t nI = ceil_div(n, ib), nJ = ceil_div(n, bj);
+    const int64_t I = at / ib, lane = at % ib, J = at / bj;
     for (int32_t ch = 0; ch < nchunks; ++ch) {
       const int64_t base = static_cast<int64_t>(ch) * a.n_strips;
       const int64_t first = row_first_strip(I, nJ, c, g);
       const int64_t spr = strips_in_row(I, nJ, c, g);
-      for (int64_t s = first; s < first + spr; ++s) {
+      for (int64_t s = first + part; s < first + spr; s += kGradParts) {
         const double* p = a.gI + ((base + s) * ib + lane) * 3;
         sx += p[0];
         sy += p[1];
         sz += p[2];
       }
       const int64_t rows = min(nI, (J + 1) * c);
-      for (int64_t Ip = 0; Ip < rows; ++Ip) {
+      for (int64_t Ip = part; Ip < rows; Ip += kGradParts) {
         int64_t ja = 0;
         const int64_t s = strip_holding(Ip, J, nJ, c, g, &ja);
         const double* p = a.gJ + ((base + s) * g * bj + (at - ja * bj)) * 3;
@@ -580,10 +587,21 @@ __global__ __launch_bounds__(256) void k_grad_reduce(AdjArgs a, int32_t nchunks,
       }
     }
   }
-  const int64_t dst = perm[d.atom_off + at];
-  grad_out[dst * 3 + 0] = sx;
-  grad_out[dst * 3 + 1] = sy;
-  grad_out[dst * 3 + 2] = sz;
+  red[part][al][0] = sx;
+  red[part][al][1] = sy;
+  red[part][al][2] = sz;
+  __syncthreads();
+  if (part == 0 && at < n) {
+    for (int k = 1; k < kGradParts; ++k) {
+      sx += red[k][al][0];
+      sy += red[k][al][1];
+      sz += red[k][al][2];
+    }
+    const int64_t dst = perm[d.atom_off + at];
+    grad_out[dst * 3 + 0] = sx;
+    grad_out[dst * 3 + 1] = sy;
+    grad_out[dst * 3 + 2] = sz;
+  }
 }
 
 bool adjoint_bj_supported(int32_t bj) { return bj == 128 || bj == 256; }
@@ -633,8 +651,8 @@ hipError_t launch_grad_reduce(const AdjArgs& a, int64_t n, int32_t nchunks, cons
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (!geometry_ok(a.geo)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_grad_reduce, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, a, nchunks, perm,
-                     grad_out);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(static_cast<uint32_t>(ceil_div(n, kGradAtoms))), dim3(kGradParts * kGradAtoms),
+                     0, st, a, nchunks, perm, grad_out);
   return hipGetLastError();
 }
 

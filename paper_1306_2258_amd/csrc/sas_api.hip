@@ -1617,7 +1617,7 @@ OrientPlan plan_orient(int64_t n, const double* q, int32_t nq_o, double r_max, d
 struct OrientLayout {
   size_t xyz = 0, tsort = 0, perm = 0, geom = 0;
   size_t upload = 0, upload_bytes = 0, chunks = 0, gl = 0, qv = 0;
-  size_t tabo = 0, apart = 0, tabd = 0, direct = 0, total = 0;
+  size_t tabo = 0, apart = 0, ored = 0, tabd = 0, direct = 0, total = 0;
 };
 
 OrientLayout orient_layout(int64_t n, int32_t T, const OrientPlan& p, int32_t nq_d, size_t direct_bytes) {
@@ -1642,6 +1642,7 @@ OrientLayout orient_layout(int64_t n, int32_t T, const OrientPlan& p, int32_t nq
   L.qv = L.upload + cb + gb;
   L.tabo = take(sizeof(float) * static_cast<size_t>(T) * p.ldo);
   L.apart = take(sizeof(double) * 2 * p.apart_elems);
+  L.ored = take(sizeof(double) * p.chunks.size() * sas::kOrientSlices * sas::kOrientQ);
   L.tabd = take(sizeof(float) * static_cast<size_t>(T) * nq_d);
   L.direct = take(direct_bytes);
   L.total = at;
@@ -1668,6 +1669,7 @@ size_t orient_bound_bytes(int64_t n, int32_t t, int32_t nq, int64_t cap) {
   b += 256 + align_up(sizeof(sas::OrientChunk) * nch) + align_up(sizeof(double) * 2 * nch * (L + 1)) +
        align_up(sizeof(double) * nq) + 256;
   b += align_up(sizeof(float) * t * nch * sas::kOrientQ);
+  b += align_up(sizeof(double) * nch * sas::kOrientSlices * sas::kOrientQ);
   if (cap > 0) b += align_up(sizeof(double) * 2 * (kOrientBlocksTarget + blocks) * sas::kWave * sas::kOrientQ);
   b += align_up(sizeof(float) * t * static_cast<size_t>(nq));
   return b;
@@ -1848,6 +1850,7 @@ sas_status sas_debye_profile_hybrid(sas_ctx* ctx, const float* coords, const int
     a.parts = plan.parts;
     a.atoms_per_part = plan.atoms_per_part;
     a.apart = reinterpret_cast<double2*>(w + L.apart);
+    a.ored = reinterpret_cast<double*>(w + L.ored);
     a.rot = orient_rot(q, nq_o, r_max, &a.dq) ? 1 : 0;
     SAS_HIP(sas::launch_orient(a, plan.total_blocks, nq_o, I_out, hs));
   }

@@ -123,6 +123,7 @@ hipError_t launch_table_grad_final(int64_t n_slices, const double* gslices, cons
 
 // Orientation-averaged profile (sas_orient.hip).
 constexpr int kOrientQ = 16;  // q values per orientation chunk (one quadrature per chunk)
+constexpr int kOrientSlices = 32;  // direction slices per chunk in the first reduce pass
 
 struct OrientChunk {
   int32_t m0, nq;    // first q (into the orientation q list) and count, m0 = chunk * kOrientQ
@@ -148,6 +149,7 @@ struct OrientArgs {
   int32_t parts;         // the atoms are split into parts (grid.y)
   int32_t atoms_per_part;
   double2* apart;        // partial amplitudes
+  double* ored;          // [chunks][kOrientSlices][kOrientQ]: per-slice sums of the reduce
   int32_t rot;           // 1: uniform q, walk exp(i q p) from the chunk's first q
   double dq;             // the grid step (rot only)
 };
