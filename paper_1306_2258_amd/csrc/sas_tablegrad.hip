@@ -124,6 +124,9 @@ __global__ __launch_bounds__(256) void k_rows_final(const float* __restrict__ ro
       v = f0[0];
     } else {
       double r = 0.0;
+      // (unrolled so that eight loads are in flight per thread; the adds keep
+      // their order)
+#pragma unroll 8
       for (int J = 0; J < nJ; ++J) r += static_cast<double>(rows[(static_cast<int64_t>(J) * rows_ld + m) * n + i]);
       v = static_cast<double>(tabp[static_cast<int64_t>(tsort[i]) * ldt + m]) + r / qm;
     }
