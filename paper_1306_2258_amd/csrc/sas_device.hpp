@@ -244,18 +244,128 @@ __device__ __forceinline__ void sin_qr_acc4_frac(const double (&q)[4], double rp
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// The type form's weight folded into the polynomial: with wc[k] = w c_k (c_k
+// the coefficients of sin(pi b) = b P(b^2)), w sin(pi b) = b (w P)(b^2) needs
+// no product by w per q.  The five products are formed once per pair; each
+// rounds once, as the product b w did, so the accuracy is that of
+// sin_qr_acc4_frac to within about one FP32 rounding of the term.
+struct SinPiW {
+  float c[5];
+};
+__device__ __forceinline__ SinPiW sinpi_weighted(float w) {
+  return {{w * kSinPi0, w * kSinPi1, w * kSinPi2, w * kSinPi3, w * kSinPi4}};
+}
+// acc[g] + b[g] (w P)(b[g]^2) for four values, stage by stage.  (The squares
+// and the first step are issued in the rotated orders 1, 2, 3, 0 and 2, 3, 0,
+// 1, which places b[g], y[g] and p[g] in three register banks: the steps read
+// three VGPRs, and three from one bank halve the issue rate.)
+__device__ __forceinline__ void acc4_weighted_sine(const float (&b)[4], const SinPiW& wc, float* acc) {
+  float y[4], p[4];
+#pragma unroll
+  for (int h = 1; h <= 4; ++h) y[h & 3] = b[h & 3] * b[h & 3];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int h = 2; h <= 5; ++h) p[h & 3] = fmaf(y[h & 3], wc.c[4], wc.c[3]);
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 2; k >= 0; --k) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], wc.c[k]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = fmac_inplace(b[g], p[g], acc[g]);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// The three direct-form evaluations of acc[g] + w sin(q[g] r) for four q
+// values from rp = r / pi, the q values uniform (SGPRs, read through the
+// scalar cache, which spares the LDS traffic of per-lane copies):
+//  - sin_qr_acc4_frac_w, the one-FMA reduction above, for 1/4 <= t < 2^19;
+//    its FMA's constant comes in the VGPR pair `magic` (one SGPR operand per
+//    instruction);
+//  - sin_qr_acc4_small_w, for t <= 1/2: b = t itself, the FP64 product
+//    rounded once to FP32 (relative error 2^-24), inside the polynomial's
+//    range, so no reduction at all;
+//  - sin_qr_acc4_exact_w, for any t: the exact reduction of sin_qr_acc,
+//    its first FMA's constant (kRoundMagic) in the VGPR pair `rmagic`.
+__device__ __forceinline__ void sin_qr_acc4_frac_w(const double (&q)[4], double rp, const SinPiW& wc, float scale,
+                                                   double magic, float* acc) {
+  double s[4];
+  float b[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_fma_f64 %0, %1, %2, %3" : "=v"(s[g]) : "s"(q[g]), "v"(rp), "v"(magic));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(__double2loint(s[g]));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_fma_f32 %0, |%1|, %2, -0.5" : "=v"(b[g]) : "v"(b[g]), "v"(scale));
+  __builtin_amdgcn_sched_barrier(0);
+  acc4_weighted_sine(b, wc, acc);
+}
+__device__ __forceinline__ void sin_qr_acc4_small_w(const double (&q)[4], double rp, const SinPiW& wc, float* acc) {
+  double t[4];
+  float b[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_mul_f64 %0, %1, %2" : "=v"(t[g]) : "s"(q[g]), "v"(rp));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(t[g]);
+  __builtin_amdgcn_sched_barrier(0);
+  acc4_weighted_sine(b, wc, acc);
+}
+__device__ __forceinline__ void sin_qr_acc4_exact_w(const double (&q)[4], double rp, const SinPiW& wc, double rmagic,
+                                                    float* acc) {
+  double s[4], x[4];
+  float b[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_fma_f64 %0, %1, %2, %3" : "=v"(s[g]) : "s"(q[g]), "v"(rp), "v"(rmagic));
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) x[g] = add_vs(s[g], -kRoundMagic);  // k = round(t)
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) asm("v_fma_f64 %0, %1, %2, -%3" : "=v"(x[g]) : "s"(q[g]), "v"(rp), "v"(x[g]));  // t - k
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(x[g]);
+  __builtin_amdgcn_sched_barrier(0);
+  // sin(pi t) = (-1)^k sin(pi (t - k)): k's parity, the low bit of s, moved
+  // to the sign bit
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    unsigned u;
+    asm("v_lshl_add_u32 %0, %1, 31, %2"
+        : "=v"(u)
+        : "v"(static_cast<unsigned>(__double2loint(s[g]))), "v"(__float_as_uint(b[g])));
+    b[g] = __uint_as_float(u);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  acc4_weighted_sine(b, wc, acc);
+}
+
 // The squared distances r^2 in [r2_lo, r2_hi) for which sin_qr_acc4_frac
 // holds its accuracy at every q in [q_lo, q_hi] (t = q r / pi from 1/4 at
 // q_lo to 2^19 at q_hi; q_lo = 0 gives an empty range).  Testing r^2 costs a
 // pair two FP64 comparisons instead of two products and two comparisons.
 struct FracRange {
-  double r2_lo, r2_hi;
+  double r2_lo, r2_hi, r2_small;
 };
+// (q = 0 adds sin(0) = 0 under every reduction, so the callers take q_lo as
+// the chunk's smallest positive q)
 __device__ __forceinline__ FracRange frac_range(double q_lo, double q_hi) {
   constexpr double kPi = 0x1.921fb54442d18p+1;
-  const double a = kFracMinT * kPi / q_lo, b = kFracMaxT * kPi / q_hi;
-  return {a * a, b * b};
+  const double a = kFracMinT * kPi / q_lo, b = kFracMaxT * kPi / q_hi, c = 0.5 * kPi / q_hi;
+  return {a * a, b * b, c * c};
 }
+// Whether a pair admits sin_qr_acc4_small_w (t <= 1/2 at every q of the chunk).
+__device__ __forceinline__ bool small_t_ok(const FracRange& fr, double r2, float w) {
+  return w == 0.f || r2 < fr.r2_small;
+}
+// The smallest positive q of a chunk of an ascending grid (q[0] when it is
+// the only value).
+__device__ __forceinline__ double chunk_q_lo(const double* q, int nqc) { return q[0] > 0.0 || nqc == 1 ? q[0] : q[1]; }
 // Whether a pair (w = 0: it adds nothing either way) admits sin_qr_acc4_frac.
 __device__ __forceinline__ bool frac_reduction_ok(const FracRange& fr, double r2, float w) {
   return w == 0.f || (r2 >= fr.r2_lo && r2 < fr.r2_hi);

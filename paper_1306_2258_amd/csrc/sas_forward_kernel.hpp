@@ -22,7 +22,7 @@
 namespace sas {
 
 // Waves per SIMD the forward kernels are built for.
-constexpr int forward_waves(int qc, int bj, bool direct) { return direct ? (bj >= 512 ? 2 : 5) : (qc > 128 ? 2 : 3); }
+constexpr int forward_waves(int qc, int bj, bool direct) { return direct ? (bj >= 512 ? 2 : 4) : (qc > 128 ? 2 : 3); }
 
 // One strip t (and q chunk) of the forward pass, by the one wave of a work-group.
 template <int QC, int BJ, bool DIRECT, bool TG>
@@ -70,13 +70,9 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
   __shared__ double tot[NT][kWave];
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
-  // direct form: this chunk's q values (0 past the end of the grid)
-  __shared__ double qv[DIRECT ? QC : 1];
-  FracRange frange{0.0, 0.0};  // from the chunk's smallest and largest q (the grid ascends)
-  if constexpr (DIRECT) {
-    for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
-    frange = frac_range(a.qdev[m0], a.qdev[m0 + nqc - 1]);
-  }
+  // direct form: the r^2 bounds of the reductions over this chunk's q values
+  FracRange frange{0.0, 0.0, 0.0};  // from the chunk's smallest positive and largest q (the grid ascends)
+  if constexpr (DIRECT) frange = frac_range(chunk_q_lo(a.qdev + m0, nqc), a.qdev[m0 + nqc - 1]);
 
 #pragma unroll 1
   for (int J = sp.Ja; J < sp.Jb; ++J) {
@@ -122,18 +118,26 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
         // arbitrary q grid: sin(q_m r)/r evaluated for every q, one pair per
         // iteration (the q steps are independent of each other).  A pair whose
         // lanes all admit the one-FMA reduction over the chunk is summed at
-        // once; the others (near-coincident atoms at the chunk's smallest q)
-        // are listed and summed after the segment with the exact reduction, so
-        // that each loop has one accumulating path (two paths in one loop make
-        // the compiler copy the accumulators after every pair).
+        // once; the others are listed, those whose lanes all have t <= 1/2
+        // (near atoms at low q) for the product form and the rest (pairs
+        // whose lanes straddle t = 1/4 or coincide) for the exact reduction,
+        // and each list is summed after the segment, so that each loop has one
+        // accumulating path (two paths in one loop make the compiler copy the
+        // accumulators after every pair).
         __shared__ int slow[DIRECT ? BJ : 1];
-        int nslow = 0;
+        __shared__ int near[DIRECT ? BJ : 1];
+        int nslow = 0, nnear = 0;
         float kScale31 = 0x1p-31f;  // (held in a VGPR: see sin_qr_acc4_frac)
         asm volatile("" : "+v"(kScale31));
+        // the q values come through the scalar cache into SGPRs (the same for
+        // every pair; the uploaded grid is padded with zeros to the table's
+        // row length, and the steps past its end are dropped), the FMAs'
+        // constants from VGPR pairs
+        using ConstDouble = const __attribute__((address_space(4))) double;
+        ConstDouble* qk = (ConstDouble*)(a.qdev + m0);
+        double kMagicV = kHalfMagic, kRoundV = kRoundMagic;
+        asm volatile("" : "+v"(kMagicV), "+v"(kRoundV));
         auto pair_setup = [&](int jl, double& rp, double& r2, float& w) {
-          // (the q values are re-read from LDS for every pair rather than
-          // held in 64 VGPRs, which would leave three waves per SIMD instead
-          // of five)
           asm volatile("" ::: "memory");
           const double4 pj = sj[jl - j0];
           const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
@@ -142,36 +146,53 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
           rp = r2 * ir * kOneOverPi;
           w = (on && jl > i) ? static_cast<float>(ir) : 0.f;
         };
+        static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+        // (each group's q values loaded before the previous group's steps)
+        auto over_q = [&](auto&& group) {
+          double qn[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) qn[k] = qk[k];
+#pragma unroll
+          for (int m = 0; m < QC; m += 4) {
+            const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
+            if (m + 4 < QC) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) qn[k] = qk[m + 4 + k];
+            }
+            group(qc, acc + m);
+          }
+        };
 #pragma unroll 1
         for (int jl = sa; jl < sb; ++jl) {
           double rp, r2;
           float w;
           pair_setup(jl, rp, r2, w);
           if (__all(frac_reduction_ok(frange, r2, w))) {
-            static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
-            // (each group's q values loaded before the previous group's steps)
-            double qn[4] = {qv[0], qv[1], qv[2], qv[3]};
-#pragma unroll
-            for (int m = 0; m < QC; m += 4) {
-              const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
-              if (m + 4 < QC) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) qn[k] = qv[m + 4 + k];
-              }
-              sin_qr_acc4_frac<false>(qc, rp, w, nullptr, kScale31, acc + m);
-            }
+            const SinPiW wc = sinpi_weighted(w);
+            over_q([&](const double(&qc)[4], float* ac) { sin_qr_acc4_frac_w(qc, rp, wc, kScale31, kMagicV, ac); });
+          } else if (__all(small_t_ok(frange, r2, w))) {
+            near[nnear] = jl;  // (every lane stores the same value)
+            ++nnear;
           } else {
-            slow[nslow] = jl;  // (every lane stores the same value)
+            slow[nslow] = jl;
             ++nslow;
           }
+        }
+#pragma unroll 1
+        for (int k = 0; k < nnear; ++k) {
+          double rp, r2;
+          float w;
+          pair_setup(near[k], rp, r2, w);
+          const SinPiW wc = sinpi_weighted(w);
+          over_q([&](const double(&qc)[4], float* ac) { sin_qr_acc4_small_w(qc, rp, wc, ac); });
         }
 #pragma unroll 1
         for (int k = 0; k < nslow; ++k) {
           double rp, r2;
           float w;
           pair_setup(slow[k], rp, r2, w);
-#pragma unroll
-          for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w, acc[m]);
+          const SinPiW wc = sinpi_weighted(w);
+          over_q([&](const double(&qc)[4], float* ac) { sin_qr_acc4_exact_w(qc, rp, wc, kRoundV, ac); });
         }
       } else {
       // two atom pairs (j, j+1) per iteration: two independent recurrence

@@ -122,10 +122,10 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
   const float* fa_row = a.tabp + static_cast<int64_t>(ta) * a.ldt + m0;
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
-  FracRange frange{0.0, 0.0};  // from the chunk's smallest and largest q (the grid ascends)
+  FracRange frange{0.0, 0.0, 0.0};  // from the chunk's smallest positive and largest q (the grid ascends)
   if constexpr (DIRECT) {
     for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
-    frange = frac_range(a.qdev[m0], a.qdev[m0 + nqc - 1]);
+    frange = frac_range(chunk_q_lo(a.qdev + m0, nqc), a.qdev[m0 + nqc - 1]);
   }
 
   const int bj = a.geo.bj;

@@ -162,7 +162,9 @@ def test_nonuniform_coincident_and_large_q(sd):
 
 
 # The direct form reduces t = q r / pi by one FP64 FMA when every lane's pair
-# has t >= 1/4 at its q chunk's smallest q, and exactly otherwise.
+# has t >= 1/4 at its q chunk's smallest positive q; pairs with t <= 1/2 at the
+# chunk's largest q take b = t itself (the product form), the rest the exact
+# reduction.
 @pytest.mark.parametrize("t_lo", [0.05, 0.2499, 0.2501, 0.3, 4.0, 3000.0])
 def test_direct_reduction_switch_pair(sd, t_lo):
     """One pair whose t at the chunk's first q sits on either side of 1/4:
@@ -177,6 +179,40 @@ def test_direct_reduction_switch_pair(sd, t_lo):
     ref = oracle.profile(m.coords, m.types, m.table, m.q)
     err = rel_err(got, ref)
     assert err.max() <= 3e-7, f"t_lo={t_lo}: {err.max():.3e} at q[{err.argmax()}]"
+
+
+@pytest.mark.parametrize("t_hi", [0.3, 0.4999, 0.5001, 0.6])
+def test_direct_product_form_edge(sd, t_hi):
+    """One pair whose t at the first chunk's largest q sits on either side of
+    1/2 (with t < 1/4 at its smallest: product form below, exact above)."""
+    say(f"direct form, one pair at t = {t_hi} for the first chunk's largest q")
+    q = W.log_grid(0.01, 1.0, 64)
+    r = t_hi * np.pi / q[31]
+    coords = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]], dtype=np.float32)
+    types = np.zeros(2, dtype=np.int32)
+    m = W.Molecule("pair", coords, types, W.gaussian_table([6.0], [0.5], q), q)
+    err = rel_err(gpu_profile(sd, m), oracle.profile(m.coords, m.types, m.table, m.q))
+    assert err.max() <= 3e-7, f"t_hi={t_hi}: {err.max():.3e} at q[{err.argmax()}]"
+
+
+def test_direct_form_chunk_starting_at_zero_q(sd):
+    """A grid that starts at q = 0 with the direct form forced: the first
+    chunk's bounds come from its smallest positive q, so distant pairs take
+    the one-FMA reduction there too (q = 0 adds sin(0) = 0 under it), near
+    ones the product form and the rest the exact reduction."""
+    say("direct form forced, uniform grid from q = 0, pairs at 1.5 to 600 A")
+    q = W.q_grid(0.0, 1.0, 64)
+    rng = np.random.default_rng(803)
+    x = np.concatenate([[0.0, 1.5, 3.0], rng.uniform(200.0, 600.0, 61)])
+    pts = np.stack([x, rng.normal(0.0, 0.5, x.size), rng.normal(0.0, 0.5, x.size)], axis=1).astype(np.float32)
+    types = rng.integers(0, 2, size=x.size).astype(np.int32)
+    m = W.Molecule("far", pts, types, W.gaussian_table([6.0, 8.0], [0.5, 0.9], q), q)
+    ctx = sd.Context(0)
+    ctx.set_form("direct")
+    got = gpu_profile(sd, m, ctx=ctx)
+    ref = oracle.profile(m.coords, m.types, m.table, m.q)
+    err = rel_err(got, ref)
+    assert err.max() <= 3e-7, f"{err.max():.3e} at q[{err.argmax()}]"
 
 
 def test_direct_reduction_switch_mixed(sd):
