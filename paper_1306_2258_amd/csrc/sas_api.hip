@@ -699,7 +699,8 @@ RowsLayout rows_layout(const sas_ctx* ctx, int64_t n, int32_t T, int32_t Nq, boo
   R.tsort = take(sizeof(int32_t) * n);
   R.perm = take(sizeof(int32_t) * n);
   R.asum = take(sizeof(double) * 2 * R.sc.n_pack * static_cast<size_t>(Nq));
-  R.upload_bytes = direct ? sizeof(double) * static_cast<size_t>(Nq) : 0;
+  // (padded with zeros to the table's row length, as in the profile's layout)
+  R.upload_bytes = direct ? sizeof(double) * static_cast<size_t>(std::max(Nq, R.sc.ldt)) : 0;
   R.upload = take(R.upload_bytes);
   R.tabp = take(sizeof(float) * static_cast<size_t>(T) * R.sc.ldt);
   R.rows = take(sizeof(float) * static_cast<size_t>(R.nJ) * Nq * n);
@@ -734,8 +735,8 @@ sas_status enqueue_table_grad_by_atom(sas_ctx* ctx, const RowsLayout& R, const f
   auto* f0 = reinterpret_cast<double*>(b + R.f0);
   const double* qdev = sc.direct ? reinterpret_cast<const double*>(b + R.upload) : nullptr;
   if (sc.direct) {
-    std::vector<char> img(R.upload_bytes);
-    std::memcpy(img.data(), grid.host, R.upload_bytes);
+    std::vector<char> img(R.upload_bytes, 0);
+    std::memcpy(img.data(), grid.host, sizeof(double) * static_cast<size_t>(Nq));
     const sas_status s2 = stage_upload_to(ctx, b + R.upload, img, st);
     if (s2 != SAS_OK) return s2;
   }

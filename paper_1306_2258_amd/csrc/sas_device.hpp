@@ -172,83 +172,29 @@ __device__ __forceinline__ float fmac_inplace(float a, float b, float acc) {
   return acc;
 }
 
-__device__ __forceinline__ float sin_qr_acc(double q, double rp, float w, float acc) {
-  const double s = fma_vvs(q, rp, kRoundMagic);
-  const double k = add_vs(s, -kRoundMagic);
-  const float x = static_cast<float>(fma(q, rp, -k));
-  const unsigned lo = static_cast<unsigned>(__double2loint(s));
-  const float xs = __uint_as_float(__float_as_uint(x) + (lo << 31));
-  const float y = xs * xs;
-  float p = fmaf(y, kSinPi4, kSinPi3);
-  p = fmaf(p, y, kSinPi2);
-  p = fmaf(p, y, kSinPi1);
-  p = fmaf(p, y, kSinPi0);
-  return fmac_inplace(xs * w, p, acc);
-}
-
-// Direct form, one-FMA reduction, for four q values at a time:
-// acc[g] + w_g sin(q[g] r) from rp = r / pi, for 1/4 <= t = q rp < 2^19,
-// with w_g = w (w wq[g] with PER_Q: the per-atom form's row factors).
-// One FMA adds 1.5 * 2^21 + 1/2, which puts the sum in [2^21, 2^22), where its
-// last bit is worth 2^-31: it holds t + 1/2 rounded to a multiple of 2^-31
-// (to nearest), and its low word read as a signed integer is v 2^31 with
-// v = t + 1/2 (mod 2), v in [-1, 1).  Then sin(pi t) = -cos(pi v) =
-// -cos(pi |v|) = sin(pi b) with b = |v| - 1/2 in [-1/2, 1/2]: one conversion
-// and one FMA give b, with no sign to apply, and sin(pi b) = b P(b^2) as in
-// the exact form.  The conversion rounds |v| to FP32, an absolute error of at
-// most 2^-25 in b, so the relative accuracy of the smallest sines holds for
-// t >= 1/4 (smaller t take the exact form).  On gfx950 FP32 additions,
-// products and FMAs whose operands are VGPRs, literals or inline constants
-// issue at twice the rate of conversions, FP64 operations and FP32
-// operations that read an SGPR; so the scale 2^-31 comes in a VGPR
+// The direct form's one-FMA reduction of t = q rp (rp = r / pi), for
+// 1/4 <= t < 2^19.  One FMA adds 1.5 * 2^21 + 1/2, which puts the sum in
+// [2^21, 2^22), where its last bit is worth 2^-31: it holds t + 1/2 rounded to
+// a multiple of 2^-31 (to nearest), and its low word read as a signed integer
+// is v 2^31 with v = t + 1/2 (mod 2), v in [-1, 1).  Then sin(pi t) =
+// -cos(pi v) = -cos(pi |v|) = sin(pi b) with b = |v| - 1/2 in [-1/2, 1/2]:
+// one conversion and one FMA give b, with no sign to apply, and
+// sin(pi b) = b P(b^2).  The conversion rounds |v| to FP32, an absolute error
+// of at most 2^-25 in b, so the relative accuracy of the smallest sines holds
+// for t >= 1/4 (smaller t take the product or the exact form).  On gfx950
+// FP32 additions, products and FMAs whose operands are VGPRs, literals or
+// inline constants issue at twice the rate of conversions, FP64 operations
+// and FP32 operations that read an SGPR; so the scale 2^-31 comes in a VGPR
 // (`scale`), and the four values' steps are issued stage by stage (one FP64
-// FMA and one conversion, then eight full-rate operations each), which lets
-// their latencies overlap.  The q values come by value: the callers load the
-// next group's from LDS before this group's steps.
+// FMA and one conversion, then the full-rate operations), which lets their
+// latencies overlap.
 constexpr double kHalfMagic = 0x1.8p+21 + 0.5;
 constexpr double kFracMinT = 0x1p-2, kFracMaxT = 0x1p+19;
-template <bool PER_Q>
-__device__ __forceinline__ void sin_qr_acc4_frac(const double (&q)[4], double rp, float w, const float* wq, float scale,
-                                                 float* acc) {
-  double s[4];
-  float b[4], y[4], p[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) s[g] = fma_vvs(q[g], rp, kHalfMagic);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(__double2loint(s[g]));
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) asm("v_fma_f32 %0, |%1|, %2, -0.5" : "=v"(b[g]) : "v"(b[g]), "v"(scale));
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) y[g] = b[g] * b[g];
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) p[g] = fmaf(y[g], kSinPi4, kSinPi3);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi2);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi1);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) p[g] = fmaf(p[g], y[g], kSinPi0);
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) b[g] *= PER_Q ? w * wq[g] : w;
-  __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-  for (int g = 0; g < 4; ++g) acc[g] = fmac_inplace(b[g], p[g], acc[g]);
-  __builtin_amdgcn_sched_barrier(0);
-}
-
 // The type form's weight folded into the polynomial: with wc[k] = w c_k (c_k
 // the coefficients of sin(pi b) = b P(b^2)), w sin(pi b) = b (w P)(b^2) needs
 // no product by w per q.  The five products are formed once per pair; each
-// rounds once, as the product b w did, so the accuracy is that of
-// sin_qr_acc4_frac to within about one FP32 rounding of the term.
+// rounds once, as a product b w would, so the accuracy is that of the
+// unweighted form to within about one FP32 rounding of the term.
 struct SinPiW {
   float c[5];
 };
@@ -259,11 +205,19 @@ __device__ __forceinline__ SinPiW sinpi_weighted(float w) {
 // and the first step are issued in the rotated orders 1, 2, 3, 0 and 2, 3, 0,
 // 1, which places b[g], y[g] and p[g] in three register banks: the steps read
 // three VGPRs, and three from one bank halve the issue rate.)
-__device__ __forceinline__ void acc4_weighted_sine(const float (&b)[4], const SinPiW& wc, float* acc) {
+// With a per-q factor fq (the per-atom form's f_b(q)), b[g] fq[g] takes the
+// place of b[g] in the last step.
+template <bool PER_Q>
+__device__ __forceinline__ void acc4_weighted_sine(float (&b)[4], const SinPiW& wc, const float* fq, float* acc) {
   float y[4], p[4];
 #pragma unroll
   for (int h = 1; h <= 4; ++h) y[h & 3] = b[h & 3] * b[h & 3];
   __builtin_amdgcn_sched_barrier(0);
+  if constexpr (PER_Q) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) b[g] *= fq[g];
+    __builtin_amdgcn_sched_barrier(0);
+  }
 #pragma unroll
   for (int h = 2; h <= 5; ++h) p[h & 3] = fmaf(y[h & 3], wc.c[4], wc.c[3]);
   __builtin_amdgcn_sched_barrier(0);
@@ -287,10 +241,12 @@ __device__ __forceinline__ void acc4_weighted_sine(const float (&b)[4], const Si
 //  - sin_qr_acc4_small_w, for t <= 1/2: b = t itself, the FP64 product
 //    rounded once to FP32 (relative error 2^-24), inside the polynomial's
 //    range, so no reduction at all;
-//  - sin_qr_acc4_exact_w, for any t: the exact reduction of sin_qr_acc,
-//    its first FMA's constant (kRoundMagic) in the VGPR pair `rmagic`.
+//  - sin_qr_acc4_exact_w, for any t: k = round(t) by one FMA that adds
+//    kRoundMagic (from the VGPR pair `rmagic`), t - k exact by a second,
+//    and the parity of k as the sign (the reduction of sincos_qr).
+template <bool PER_Q = false>
 __device__ __forceinline__ void sin_qr_acc4_frac_w(const double (&q)[4], double rp, const SinPiW& wc, float scale,
-                                                   double magic, float* acc) {
+                                                   double magic, float* acc, const float* fq = nullptr) {
   double s[4];
   float b[4];
 #pragma unroll
@@ -302,9 +258,11 @@ __device__ __forceinline__ void sin_qr_acc4_frac_w(const double (&q)[4], double 
 #pragma unroll
   for (int g = 0; g < 4; ++g) asm("v_fma_f32 %0, |%1|, %2, -0.5" : "=v"(b[g]) : "v"(b[g]), "v"(scale));
   __builtin_amdgcn_sched_barrier(0);
-  acc4_weighted_sine(b, wc, acc);
+  acc4_weighted_sine<PER_Q>(b, wc, fq, acc);
 }
-__device__ __forceinline__ void sin_qr_acc4_small_w(const double (&q)[4], double rp, const SinPiW& wc, float* acc) {
+template <bool PER_Q = false>
+__device__ __forceinline__ void sin_qr_acc4_small_w(const double (&q)[4], double rp, const SinPiW& wc, float* acc,
+                                                    const float* fq = nullptr) {
   double t[4];
   float b[4];
 #pragma unroll
@@ -313,10 +271,11 @@ __device__ __forceinline__ void sin_qr_acc4_small_w(const double (&q)[4], double
 #pragma unroll
   for (int g = 0; g < 4; ++g) b[g] = static_cast<float>(t[g]);
   __builtin_amdgcn_sched_barrier(0);
-  acc4_weighted_sine(b, wc, acc);
+  acc4_weighted_sine<PER_Q>(b, wc, fq, acc);
 }
+template <bool PER_Q = false>
 __device__ __forceinline__ void sin_qr_acc4_exact_w(const double (&q)[4], double rp, const SinPiW& wc, double rmagic,
-                                                    float* acc) {
+                                                    float* acc, const float* fq = nullptr) {
   double s[4], x[4];
   float b[4];
 #pragma unroll
@@ -342,13 +301,14 @@ __device__ __forceinline__ void sin_qr_acc4_exact_w(const double (&q)[4], double
     b[g] = __uint_as_float(u);
   }
   __builtin_amdgcn_sched_barrier(0);
-  acc4_weighted_sine(b, wc, acc);
+  acc4_weighted_sine<PER_Q>(b, wc, fq, acc);
 }
 
-// The squared distances r^2 in [r2_lo, r2_hi) for which sin_qr_acc4_frac
+// The squared distances r^2 in [r2_lo, r2_hi) for which sin_qr_acc4_frac_w
 // holds its accuracy at every q in [q_lo, q_hi] (t = q r / pi from 1/4 at
-// q_lo to 2^19 at q_hi; q_lo = 0 gives an empty range).  Testing r^2 costs a
-// pair two FP64 comparisons instead of two products and two comparisons.
+// q_lo to 2^19 at q_hi; q_lo = 0 gives an empty range), and those below
+// r2_small, for which sin_qr_acc4_small_w does (t <= 1/2 at q_hi).  Testing
+// r^2 costs a pair FP64 comparisons instead of products and comparisons.
 struct FracRange {
   double r2_lo, r2_hi, r2_small;
 };
@@ -366,7 +326,7 @@ __device__ __forceinline__ bool small_t_ok(const FracRange& fr, double r2, float
 // The smallest positive q of a chunk of an ascending grid (q[0] when it is
 // the only value).
 __device__ __forceinline__ double chunk_q_lo(const double* q, int nqc) { return q[0] > 0.0 || nqc == 1 ? q[0] : q[1]; }
-// Whether a pair (w = 0: it adds nothing either way) admits sin_qr_acc4_frac.
+// Whether a pair (w = 0: it adds nothing either way) admits sin_qr_acc4_frac_w.
 __device__ __forceinline__ bool frac_reduction_ok(const FracRange& fr, double r2, float w) {
   return w == 0.f || (r2 >= fr.r2_lo && r2 < fr.r2_hi);
 }

@@ -127,7 +127,7 @@ __device__ __forceinline__ void forward_strip(const ForwardArgs& a, int64_t t, i
         __shared__ int slow[DIRECT ? BJ : 1];
         __shared__ int near[DIRECT ? BJ : 1];
         int nslow = 0, nnear = 0;
-        float kScale31 = 0x1p-31f;  // (held in a VGPR: see sin_qr_acc4_frac)
+        float kScale31 = 0x1p-31f;  // (held in a VGPR: see the one-FMA reduction)
         asm volatile("" : "+v"(kScale31));
         // the q values come through the scalar cache into SGPRs (the same for
         // every pair; the uploaded grid is padded with zeros to the table's

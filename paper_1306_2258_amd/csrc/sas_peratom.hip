@@ -92,7 +92,6 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
   __shared__ double4 sj[kPaSub];
   __shared__ __align__(16) float fj[kPaSub][QC];
   __shared__ double tot[NT][kWave];
-  __shared__ double qv[DIRECT ? QC : 1];
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
   const int s = ROWS ? 0 : find_struct_by_strip(a.sd, t);
@@ -123,10 +122,7 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
 #pragma unroll
   for (int k = 0; k < NT; ++k) tot[k][lane] = 0.0;
   FracRange frange{0.0, 0.0, 0.0};  // from the chunk's smallest positive and largest q (the grid ascends)
-  if constexpr (DIRECT) {
-    for (int k = lane; k < QC; k += kWave) qv[k] = k < nqc ? a.qdev[m0 + k] : 0.0;
-    frange = frac_range(chunk_q_lo(a.qdev + m0, nqc), a.qdev[m0 + nqc - 1]);
-  }
+  if constexpr (DIRECT) frange = frac_range(chunk_q_lo(a.qdev + m0, nqc), a.qdev[m0 + nqc - 1]);
 
   const int bj = a.geo.bj;
 #pragma unroll 1
@@ -171,12 +167,18 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
       __syncthreads();
       if constexpr (DIRECT) {
         // the one-FMA reduction for pairs whose lanes all admit it over the
-        // chunk; the rest are listed and summed after the run with the exact
-        // reduction (one accumulating path per loop, as in the type form)
+        // chunk; the rest are listed, for the product form or the exact
+        // reduction, and summed after the run (one accumulating path per
+        // loop, as in the type form; q through the scalar cache as there)
         __shared__ int slow[DIRECT ? kPaSub : 1];
-        int nslow = 0;
-        float kScale31 = 0x1p-31f;  // (held in a VGPR: see sin_qr_acc4_frac)
+        __shared__ int near[DIRECT ? kPaSub : 1];
+        int nslow = 0, nnear = 0;
+        float kScale31 = 0x1p-31f;  // (held in a VGPR: see the one-FMA reduction)
         asm volatile("" : "+v"(kScale31));
+        using ConstDouble = const __attribute__((address_space(4))) double;
+        ConstDouble* qk = (ConstDouble*)(a.qdev + m0);
+        double kMagicV = kHalfMagic, kRoundV = kRoundMagic;
+        asm volatile("" : "+v"(kMagicV), "+v"(kRoundV));
         auto pair_setup = [&](int jl, double& rp, double& r2, float& w) {
           asm volatile("" ::: "memory");
           const double4 pj = sj[jl - u0];
@@ -186,6 +188,22 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           rp = r2 * ir * kOneOverPi;
           w = (vi && (ROWS ? jl != i : jl > i)) ? static_cast<float>(ir) : 0.f;
         };
+        static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
+        // (each group's q values loaded before the previous group's steps)
+        auto over_q = [&](auto&& group) {
+          double qn[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) qn[k] = qk[k];
+#pragma unroll
+          for (int m = 0; m < QC; m += 4) {
+            const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
+            if (m + 4 < QC) {
+#pragma unroll
+              for (int k = 0; k < 4; ++k) qn[k] = qk[m + 4 + k];
+            }
+            group(qc, m);
+          }
+        };
 #pragma unroll 1
         for (int jl = u0; jl < u0 + ns; ++jl) {
           double rp, r2;
@@ -193,22 +211,27 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           pair_setup(jl, rp, r2, w);
           if (__all(frac_reduction_ok(frange, r2, w))) {
             const float* fb = fj[jl - u0];
-            static_assert(QC % 4 == 0, "the direct form's q chunk holds groups of four");
-            // (each group's q values loaded before the previous group's steps)
-            double qn[4] = {qv[0], qv[1], qv[2], qv[3]};
-#pragma unroll
-            for (int m = 0; m < QC; m += 4) {
-              const double qc[4] = {qn[0], qn[1], qn[2], qn[3]};
-              if (m + 4 < QC) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) qn[k] = qv[m + 4 + k];
-              }
-              sin_qr_acc4_frac<true>(qc, rp, w, fb + m, kScale31, acc + m);
-            }
+            const SinPiW wc = sinpi_weighted(w);
+            over_q([&](const double(&qc)[4], int m) {
+              sin_qr_acc4_frac_w<true>(qc, rp, wc, kScale31, kMagicV, acc + m, fb + m);
+            });
+          } else if (__all(small_t_ok(frange, r2, w))) {
+            near[nnear] = jl;  // (every lane stores the same value)
+            ++nnear;
           } else {
-            slow[nslow] = jl;  // (every lane stores the same value)
+            slow[nslow] = jl;
             ++nslow;
           }
+        }
+#pragma unroll 1
+        for (int k = 0; k < nnear; ++k) {
+          const int jl = near[k];
+          double rp, r2;
+          float w;
+          pair_setup(jl, rp, r2, w);
+          const float* fb = fj[jl - u0];
+          const SinPiW wc = sinpi_weighted(w);
+          over_q([&](const double(&qc)[4], int m) { sin_qr_acc4_small_w<true>(qc, rp, wc, acc + m, fb + m); });
         }
 #pragma unroll 1
         for (int k = 0; k < nslow; ++k) {
@@ -217,8 +240,8 @@ __global__ __launch_bounds__(kWave, DIRECT ? 4 : (QC > 128 ? 2 : 3)) void k_forw
           float w;
           pair_setup(jl, rp, r2, w);
           const float* fb = fj[jl - u0];
-#pragma unroll
-          for (int m = 0; m < QC; ++m) acc[m] = sin_qr_acc(qv[m], rp, w * fb[m], acc[m]);
+          const SinPiW wc = sinpi_weighted(w);
+          over_q([&](const double(&qc)[4], int m) { sin_qr_acc4_exact_w<true>(qc, rp, wc, kRoundV, acc + m, fb + m); });
         }
       } else {
         // two pairs per iteration, as in the type-segment form; an odd run
