@@ -672,7 +672,7 @@ struct RowsLayout {
   Schedule sc;
   int32_t nJ = 0, end_bit = 1;
   size_t xyz = 0, tsort = 0, perm = 0, asum = 0, upload = 0, upload_bytes = 0, tabp = 0, rows = 0, srow = 0;
-  size_t keys = 0, atoms = 0, f0 = 0, tmp = 0, tmp_bytes = 0, total = 0;
+  size_t keys = 0, atoms = 0, f0 = 0, part = 0, tmp = 0, tmp_bytes = 0, total = 0;
 };
 
 // J blocks of at most 512 atoms (the FP32 sum of one block is exact enough,
@@ -708,6 +708,7 @@ RowsLayout rows_layout(const sas_ctx* ctx, int64_t n, int32_t T, int32_t Nq, boo
   R.keys = take(sizeof(int32_t) * n);
   R.atoms = take(sizeof(int32_t) * n);
   R.f0 = take(sizeof(double));
+  R.part = take(sizeof(double) * static_cast<size_t>(Nq) * sas::rows_final_blocks(static_cast<int32_t>(n)));
   size_t tb = 0;
   if (n > 0 && sas::sort_atoms_by_type(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, static_cast<int32_t>(n),
                                        R.end_bit, nullptr) != hipSuccess)
@@ -733,6 +734,7 @@ sas_status enqueue_table_grad_by_atom(sas_ctx* ctx, const RowsLayout& R, const f
   auto* keys = reinterpret_cast<int32_t*>(b + R.keys);
   auto* atoms = reinterpret_cast<int32_t*>(b + R.atoms);
   auto* f0 = reinterpret_cast<double*>(b + R.f0);
+  auto* part = reinterpret_cast<double*>(b + R.part);
   const double* qdev = sc.direct ? reinterpret_cast<const double*>(b + R.upload) : nullptr;
   if (sc.direct) {
     std::vector<char> img(R.upload_bytes, 0);
@@ -769,8 +771,8 @@ sas_status enqueue_table_grad_by_atom(sas_ctx* ctx, const RowsLayout& R, const f
   }
   SAS_HIP(sas::launch_rows_f0(asum, sc.n_pack, Nq, f0, st));
   SAS_HIP(sas::launch_rows_final(rows, R.nJ, Nq, static_cast<int32_t>(n), Nq, tabp, sc.ldt, tsort, grid.q0, grid.dq,
-                                 qdev, f0, srow, st));
-  if (I_out) SAS_HIP(sas::launch_rows_profile(srow, tabp, sc.ldt, tsort, static_cast<int32_t>(n), Nq, I_out, st));
+                                 qdev, f0, srow, part, st));
+  if (I_out) SAS_HIP(sas::launch_rows_profile(part, static_cast<int32_t>(n), Nq, I_out, st));
   if (n > 0) {
     size_t tb = R.tmp_bytes;
     SAS_HIP(sas::sort_atoms_by_type(b + R.tmp, &tb, tsort, keys, perm, atoms, static_cast<int32_t>(n), R.end_bit, st));

@@ -177,12 +177,15 @@ hipError_t launch_forward_pa_rows(const ForwardArgs& a, int32_t qc_template, hip
 // the stable sort of atoms by type (hipCUB radix sort; *tmp_bytes is the
 // temporary size, queried with tmp = NULL); the per-type sums times 2 w_m.
 hipError_t launch_rows_f0(const double* asum, int64_t n_pack, int32_t Nq, double* f0, hipStream_t st);
+// (the final step also writes each work-group's sums of f_i S_i, [Nq] rows of
+// rows_final_blocks(n) values in `part`, from which the profile is summed;
+// ldt a multiple of 4)
+constexpr int kRowsAtoms = 256;
+int32_t rows_final_blocks(int32_t n);
 hipError_t launch_rows_final(const float* rows, int32_t nJ, int32_t rows_ld, int32_t n, int32_t Nq, const float* tabp,
-                             int32_t ldt,
-                             const int32_t* tsort, double q0, double dq, const double* qdev, const double* f0,
-                             double* srow, hipStream_t st);
-hipError_t launch_rows_profile(const double* srow, const float* tabp, int32_t ldt, const int32_t* tsort, int32_t n,
-                               int32_t Nq, double* I_out, hipStream_t st);
+                             int32_t ldt, const int32_t* tsort, double q0, double dq, const double* qdev,
+                             const double* f0, double* srow, double* part, hipStream_t st);
+hipError_t launch_rows_profile(const double* part, int32_t n, int32_t Nq, double* I_out, hipStream_t st);
 hipError_t sort_atoms_by_type(void* tmp, size_t* tmp_bytes, const int32_t* keys_in, int32_t* keys_out,
                               const int32_t* vals_in, int32_t* vals_out, int32_t n, int32_t end_bit, hipStream_t st);
 hipError_t launch_rows_by_type(const int32_t* keys, const int32_t* atoms, int32_t n, const double* srow, int32_t T,

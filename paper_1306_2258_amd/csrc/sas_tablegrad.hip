@@ -18,7 +18,8 @@
 //            J block, in FP32;
 //   final    S_i = f_i + R_i / q_m (J blocks summed in FP64, in order); at q_m = 0,
 //            S_i = sum_j f_j(0);
-//   profile  I(q_m) = sum_i f_i S_i, one work-group per q, fixed order;
+//   profile  I(q_m) = sum_i f_i S_i: sums over the final step's work-groups
+//            (256 atoms each), then those sums in order, one wave per q;
 //   by type  atoms sorted by type (stable radix sort, so each type's atoms
 //            stay in index order), then one thread per (type, q) sums its
 //            atoms' S_i in that order and writes 2 w_m times the sum.
@@ -107,68 +108,99 @@ hipError_t launch_rows_f0(const double* asum, int64_t n_pack, int32_t Nq, double
   return hipGetLastError();
 }
 
-// Grid-stride over (q, atom) with the atom fastest.
-__global__ __launch_bounds__(256) void k_rows_final(const float* __restrict__ rows, int32_t nJ, int32_t rows_ld,
-                                                    int32_t n, int32_t Nq, const float* __restrict__ tabp, int32_t ldt,
-                                                    const int32_t* __restrict__ tsort, double q0, double dq,
-                                                    const double* __restrict__ qdev, const double* __restrict__ f0,
-                                                    double* __restrict__ srow) {
-  const int64_t total = static_cast<int64_t>(n) * Nq;
+__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, int64_t count) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < total; k += stride) {
-    const int m = static_cast<int>(k / n);
-    const int64_t i = k - static_cast<int64_t>(m) * n;
-    const double qm = qdev ? qdev[m] : q0 + m * dq;
-    double v;
-    if (qm == 0.0) {
-      v = f0[0];
-    } else {
-      double r = 0.0;
-      // (unrolled so that eight loads are in flight per thread; the adds keep
-      // their order)
-#pragma unroll 8
-      for (int J = 0; J < nJ; ++J) r += static_cast<double>(rows[(static_cast<int64_t>(J) * rows_ld + m) * n + i]);
-      v = static_cast<double>(tabp[static_cast<int64_t>(tsort[i]) * ldt + m]) + r / qm;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count; k += stride) p[k] = 0.0;
+}
+
+// One thread per atom and four consecutive q (a work-group: 256 atoms by
+// four q; blockIdx.y the q group): the atom's four form factors in one
+// 16-byte read (ldt and the group start are multiples of 4), the J blocks
+// summed in FP64 in order (unrolled, so that many loads are in flight), and
+// the work-group's sums of f_i S_i per q written to part[m][blockIdx.x] for
+// the profile.
+__global__ __launch_bounds__(kRowsAtoms) void k_rows_final(const float* __restrict__ rows, int32_t nJ,
+                                                           int32_t rows_ld, int32_t n, int32_t Nq,
+                                                           const float* __restrict__ tabp, int32_t ldt,
+                                                           const int32_t* __restrict__ tsort, double q0, double dq,
+                                                           const double* __restrict__ qdev,
+                                                           const double* __restrict__ f0, double* __restrict__ srow,
+                                                           double* __restrict__ part) {
+  __shared__ double red[4][kRowsAtoms];
+  const int i = blockIdx.x * kRowsAtoms + threadIdx.x;
+  const int m0 = blockIdx.y * 4;
+  double fs[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n) {
+    const float4 f4 = *reinterpret_cast<const float4*>(tabp + static_cast<int64_t>(tsort[i]) * ldt + m0);
+    const float f[4] = {f4.x, f4.y, f4.z, f4.w};
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
+    // (rows past the grid's end read the last row, in bounds, and are dropped)
+    const float* col[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) col[g] = rows + static_cast<int64_t>(min(m0 + g, Nq - 1)) * n + i;
+    const int64_t jstride = static_cast<int64_t>(rows_ld) * n;
+#pragma unroll 4
+    for (int J = 0; J < nJ; ++J) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) r[g] += static_cast<double>(col[g][J * jstride]);
     }
-    srow[k] = v;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int m = m0 + g;
+      if (m >= Nq) break;
+      const double qm = qdev ? qdev[m] : q0 + m * dq;
+      const double v = qm == 0.0 ? f0[0] : static_cast<double>(f[g]) + r[g] / qm;
+      srow[static_cast<int64_t>(m) * n + i] = v;
+      fs[g] = static_cast<double>(f[g]) * v;
+    }
   }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) red[g][threadIdx.x] = fs[g];
+  __syncthreads();
+  for (int h = kRowsAtoms / 2; h >= 1; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) red[g][threadIdx.x] += red[g][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4 && m0 + static_cast<int>(threadIdx.x) < Nq)
+    part[static_cast<int64_t>(m0 + threadIdx.x) * gridDim.x + blockIdx.x] = red[threadIdx.x][0];
 }
 
 int64_t grid_stride_blocks(int64_t total) { return std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 65536)); }
 
+int32_t rows_final_blocks(int32_t n) { return static_cast<int32_t>(ceil_div(static_cast<int64_t>(n), kRowsAtoms)); }
+
 hipError_t launch_rows_final(const float* rows, int32_t nJ, int32_t rows_ld, int32_t n, int32_t Nq, const float* tabp,
                              int32_t ldt, const int32_t* tsort, double q0, double dq, const double* qdev,
-                             const double* f0, double* srow, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  const int64_t blocks = grid_stride_blocks(static_cast<int64_t>(n) * Nq);
-  hipLaunchKernelGGL(k_rows_final, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, st, rows, nJ, rows_ld, n, Nq,
-                     tabp, ldt, tsort, q0, dq, qdev, f0, srow);
+                             const double* f0, double* srow, double* part, hipStream_t st) {
+  if (n <= 0 || Nq <= 0) return hipSuccess;
+  if (ldt % 4 != 0 || ldt < (Nq + 3) / 4 * 4) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<uint32_t>(rows_final_blocks(n)), static_cast<uint32_t>((Nq + 3) / 4));
+  hipLaunchKernelGGL(k_rows_final, grid, dim3(kRowsAtoms), 0, st, rows, nJ, rows_ld, n, Nq, tabp, ldt, tsort, q0, dq,
+                     qdev, f0, srow, part);
   return hipGetLastError();
 }
 
-// One work-group per q: sum_i f_i S_i, threads strided over the atoms, then a
-// fixed tree.
-__global__ __launch_bounds__(256) void k_rows_profile(const double* __restrict__ srow, const float* __restrict__ tabp,
-                                                      int32_t ldt, const int32_t* __restrict__ tsort, int32_t n,
-                                                      int32_t Nq, double* __restrict__ I_out) {
-  __shared__ double red[256];
+// I(q_m) = sum of the work-groups' parts of row m in order: one wave per q,
+// lane k adding parts k, k + 64, ... in order, then a fixed shuffle tree.
+__global__ __launch_bounds__(kWave) void k_rows_profile(const double* __restrict__ part, int32_t nparts,
+                                                        double* __restrict__ I_out) {
   const int m = blockIdx.x;
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
-    acc = fma(static_cast<double>(tabp[static_cast<int64_t>(tsort[i]) * ldt + m]), srow[static_cast<int64_t>(m) * n + i],
-              acc);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
-    if (static_cast<int>(threadIdx.x) < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) I_out[m] = red[0];
+  for (int b = threadIdx.x; b < nparts; b += kWave) acc += part[static_cast<int64_t>(m) * nparts + b];
+  for (int h = kWave / 2; h >= 1; h >>= 1) acc += __shfl_down(acc, h, kWave);
+  if (threadIdx.x == 0) I_out[m] = acc;
 }
 
-hipError_t launch_rows_profile(const double* srow, const float* tabp, int32_t ldt, const int32_t* tsort, int32_t n,
-                               int32_t Nq, double* I_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_rows_profile, dim3(static_cast<uint32_t>(Nq)), dim3(256), 0, st, srow, tabp, ldt, tsort, n, Nq,
+hipError_t launch_rows_profile(const double* part, int32_t n, int32_t Nq, double* I_out, hipStream_t st) {
+  if (Nq <= 0) return hipSuccess;
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, st, I_out, static_cast<int64_t>(Nq));
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_rows_profile, dim3(static_cast<uint32_t>(Nq)), dim3(kWave), 0, st, part, rows_final_blocks(n),
                      I_out);
   return hipGetLastError();
 }
@@ -195,11 +227,6 @@ __global__ __launch_bounds__(256) void k_rows_by_type(const int32_t* __restrict_
     for (int64_t e = k; e < n && keys[e] == t; ++e) s += srow[static_cast<int64_t>(m) * n + atoms[e]];
     grad_table[static_cast<int64_t>(t) * Nq + m] = 2.0 * w[m] * s;
   }
-}
-
-__global__ __launch_bounds__(256) void k_fill_zero(double* __restrict__ p, int64_t count) {
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count; k += stride) p[k] = 0.0;
 }
 
 hipError_t launch_rows_by_type(const int32_t* keys, const int32_t* atoms, int32_t n, const double* srow, int32_t T,
