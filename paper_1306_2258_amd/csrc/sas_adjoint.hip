@@ -122,13 +122,32 @@ __device__ __forceinline__ double adj_force_direct(bool valid, double ir, float 
   return valid ? 2.0 * ir * ir * (static_cast<double>(c) - static_cast<double>(s) * ir) : 0.0;
 }
 
+// The minimum and maximum over the 64 lanes, by the same DPP steps (lanes
+// outside a step's rows take the identity), returned from lane 63.
+template <int CTRL, int ROW_MASK, bool MAX>
+__device__ __forceinline__ float dpp_ext(float v) {
+  const float id = MAX ? 0.f : __builtin_huge_valf();
+  const float moved =
+      __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(id), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+  return MAX ? fmaxf(v, moved) : fminf(v, moved);
+}
+template <bool MAX>
+__device__ __forceinline__ float wave_extreme(float v) {
+  v = dpp_ext<0xB1, 0xF, MAX>(v);
+  v = dpp_ext<0x4E, 0xF, MAX>(v);
+  v = dpp_ext<0x141, 0xF, MAX>(v);
+  v = dpp_ext<0x140, 0xF, MAX>(v);
+  v = dpp_ext<0x142, 0xA, MAX>(v);
+  v = dpp_ext<0x143, 0xC, MAX>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 template <int BJ, bool DIRECT>
 __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
   __shared__ double4 sj[BJ];
   __shared__ float4 ul4[kAdjQ / 4];
   __shared__ float4 vl4[kAdjQ / 4];
   __shared__ double gjl[BJ * 3];
-  __shared__ double qvl[DIRECT ? kAdjQ : 1];
   float* ul = reinterpret_cast<float*>(ul4);
   float* vl = reinterpret_cast<float*>(vl4);
 
@@ -201,11 +220,23 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
           }
           ul[m] = u;
           vl[m] = v;
-          if constexpr (DIRECT) qvl[m] = qm;
         }
         __syncthreads();
         const float u0 = ul[0];
         if constexpr (DIRECT) {
+          // q through the scalar cache (uniform; the upload is padded past the
+          // chunk's last group of four), weights from LDS; per group of four
+          // q the cheapest evaluation that holds for every lane's pairs: the
+          // product form when t = q r / pi <= 1/2 at the group's largest q,
+          // the one-FMA reduction when 1/4 <= t < 2^19 over the group, the
+          // exact reduction otherwise.  The bounds are on q: the wave's
+          // extremes of 1/r (FP32; a bound off by a rounding moves t by
+          // 2^-24 relative, well inside each form's margin).
+          using ConstDouble = const __attribute__((address_space(4))) double;
+          ConstDouble* qk = (ConstDouble*)(a.qdev + m0);
+          double kMagicV = kHalfMagic, kRoundV = kRoundMagic;
+          float kScale31 = 0x1p-31f;
+          asm volatile("" : "+v"(kMagicV), "+v"(kRoundV), "+v"(kScale31));
 #pragma unroll 1
           for (int jl = sa; jl < sb; ++jl) {
             const double4 pj = sj[jl - j0];
@@ -216,17 +247,39 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
             const bool va = mine1 && jl > i1 && ra2 > 0.0, vb = mine2 && jl > i2 && rb2 > 0.0;
             const double ira = rsqrt_f64(fmax(ra2, 1e-60)), irb = rsqrt_f64(fmax(rb2, 1e-60));
             const double rpa = fmax(ra2, 1e-60) * ira * kOneOverPi, rpb = fmax(rb2, 1e-60) * irb * kOneOverPi;
+            const float ifa = static_cast<float>(ira), ifb = static_cast<float>(irb);
+            const float ir_min =
+                wave_extreme<false>(fminf(va ? ifa : __builtin_huge_valf(), vb ? ifb : __builtin_huge_valf()));
+            const float ir_max = wave_extreme<true>(fmaxf(va ? ifa : 0.f, vb ? ifb : 0.f));
+            constexpr double kPi = 0x1.921fb54442d18p+1;
+            const double q_small = 0.5 * kPi * ir_min;     // t <= 1/2 below
+            const double q_frac = 0.25 * kPi * ir_max;     // t >= 1/4 above
+            const double q_huge = 0x1p+19 * kPi * ir_min;  // t < 2^19 below
             float ca = 0.f, sa2 = 0.f, cb = 0.f, sb2 = 0.f;
-#pragma unroll 2
-            for (int m = 0; m < nqa; ++m) {
-              const double qm = qvl[m];
-              const float u = ul[m], v = vl[m];
-              const SinCosF ea = sincos_qr(qm, rpa);
-              const SinCosF eb = sincos_qr(qm, rpb);
-              ca = fmaf(u, ea.c, ca);
-              sa2 = fmaf(v, ea.s, sa2);
-              cb = fmaf(u, eb.c, cb);
-              sb2 = fmaf(v, eb.s, sb2);
+#pragma unroll 1
+            for (int m = 0; m < nqa; m += 4) {
+              const float4 u4 = ul4[m >> 2], v4 = vl4[m >> 2];
+              const float u[4] = {u4.x, u4.y, u4.z, u4.w}, v[4] = {v4.x, v4.y, v4.z, v4.w};
+              double q[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) q[k] = qk[m + k];
+              const double q_last = qk[min(m + 3, nqa - 1)];
+              auto acc4 = [&](auto&& eval) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  const SinCosF ea = eval(q[k], rpa), eb = eval(q[k], rpb);
+                  ca = fmaf(u[k], ea.c, ca);
+                  sa2 = fmaf(v[k], ea.s, sa2);
+                  cb = fmaf(u[k], eb.c, cb);
+                  sb2 = fmaf(v[k], eb.s, sb2);
+                }
+              };
+              if (q_last <= q_small)
+                acc4([&](double qq, double rp) { return sincos_qr_small(qq, rp); });
+              else if (q[0] >= q_frac && q_last < q_huge)
+                acc4([&](double qq, double rp) { return sincos_qr_frac(qq, rp, kMagicV, kScale31); });
+              else
+                acc4([&](double qq, double rp) { return sincos_qr_exact(qq, rp, kRoundV); });
             }
             const double GA = adj_force_direct(va, ira, ca, sa2);
             const double GB = adj_force_direct(vb, irb, cb, sb2);

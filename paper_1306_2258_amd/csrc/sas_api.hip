@@ -427,9 +427,10 @@ Layout make_layout(const Schedule& sc, int32_t T, int32_t Nq) {
   }
   {
     const size_t dbytes = sc.S > 1 ? align_up(sizeof(StructDesc) * sc.S) : 0;
-    // (the q grid is padded with zeros to the table's row length, so that
-    // the pair kernels read every chunk's full q groups in bounds)
-    const size_t qbytes = sc.direct ? sizeof(double) * static_cast<size_t>(std::max(Nq, sc.ldt)) : 0;
+    // (the q grid is padded with zeros to the table's row length and at
+    // least to a multiple of 8, so that the pair kernels read every chunk's
+    // full q groups in bounds)
+    const size_t qbytes = sc.direct ? sizeof(double) * static_cast<size_t>(std::max(sc.ldt, (Nq + 7) / 8 * 8)) : 0;
     L.upload_bytes = dbytes + qbytes;
     L.upload = take(L.upload_bytes);
     L.desc = L.upload;

@@ -165,6 +165,57 @@ __device__ __forceinline__ SinCosF sincos_qr(double q, double rp) {
   return r;
 }
 
+// sin(pi b) and cos(pi b) for |b| <= 1/2 by the two polynomials above.
+__device__ __forceinline__ SinCosF sincos_pi(float b) {
+  const float y = b * b;
+  float p = fmaf(y, kSinPi4, kSinPi3);
+  p = fmaf(p, y, kSinPi2);
+  p = fmaf(p, y, kSinPi1);
+  p = fmaf(p, y, kSinPi0);
+  float c = fmaf(y, kCosPi5, kCosPi4);
+  c = fmaf(c, y, kCosPi3);
+  c = fmaf(c, y, kCosPi2);
+  c = fmaf(c, y, kCosPi1);
+  c = fmaf(c, y, kCosPi0);
+  return {b * p, c};
+}
+// The direct adjoint's three evaluations of sin(q r) and cos(q r) from
+// rp = r / pi, with q uniform (an SGPR):
+//  - sincos_qr_small for t = q rp <= 1/2: b = t, the FP64 product rounded
+//    once to FP32, no reduction;
+//  - sincos_qr_frac for 1/4 <= t < 2^19: the one-FMA reduction (b = |v| - 1/2
+//    with v = t + 1/2 mod 2, v in [-1, 1)); sin(pi t) = sin(pi b) and
+//    cos(pi t) = sin(pi v) = sign(v) cos(pi b), the sign being that of the
+//    sum's low word; `magic` (1.5 2^21 + 1/2) and `scale` (2^-31) in VGPRs;
+//  - sincos_qr_exact for any t: the reduction of sincos_qr, its first FMA's
+//    constant in the VGPR pair `rmagic`.
+__device__ __forceinline__ SinCosF sincos_qr_small(double q, double rp) {
+  double t;
+  asm("v_mul_f64 %0, %1, %2" : "=v"(t) : "s"(q), "v"(rp));
+  return sincos_pi(static_cast<float>(t));
+}
+__device__ __forceinline__ SinCosF sincos_qr_frac(double q, double rp, double magic, float scale) {
+  double s;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(s) : "s"(q), "v"(rp), "v"(magic));
+  const unsigned lo = static_cast<unsigned>(__double2loint(s));
+  float b = static_cast<float>(static_cast<int>(lo));
+  asm("v_fma_f32 %0, |%1|, %2, -0.5" : "=v"(b) : "v"(b), "v"(scale));
+  SinCosF r = sincos_pi(b);
+  r.c = __uint_as_float(__float_as_uint(r.c) ^ (lo & 0x80000000u));
+  return r;
+}
+__device__ __forceinline__ SinCosF sincos_qr_exact(double q, double rp, double rmagic) {
+  double s, x;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(s) : "s"(q), "v"(rp), "v"(rmagic));
+  const double k = add_vs(s, -kRoundMagic);
+  asm("v_fma_f64 %0, %1, %2, -%3" : "=v"(x) : "s"(q), "v"(rp), "v"(k));
+  const unsigned flip = static_cast<unsigned>(__double2loint(s)) << 31;
+  SinCosF r = sincos_pi(static_cast<float>(x));
+  r.s = __uint_as_float(__float_as_uint(r.s) + flip);
+  r.c = __uint_as_float(__float_as_uint(r.c) + flip);
+  return r;
+}
+
 // acc + a * b written in place (v_fmac_f32), so that the accumulators of the
 // direct forms' two sine evaluations keep their registers.
 __device__ __forceinline__ float fmac_inplace(float a, float b, float acc) {
