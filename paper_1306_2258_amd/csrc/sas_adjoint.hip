@@ -224,8 +224,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
         __syncthreads();
         const float u0 = ul[0];
         if constexpr (DIRECT) {
-          // q through the scalar cache (uniform; the upload is padded past the
-          // chunk's last group of four), weights from LDS; per group of four
+          // q through the scalar cache (uniform), weights from LDS; per group of four
           // q the cheapest evaluation that holds for every lane's pairs: the
           // product form when t = q r / pi <= 1/2 at the group's largest q,
           // the one-FMA reduction when 1/4 <= t < 2^19 over the group, the
@@ -260,10 +259,13 @@ __global__ __launch_bounds__(kWave) void k_adjoint(AdjArgs a) {
             for (int m = 0; m < nqa; m += 4) {
               const float4 u4 = ul4[m >> 2], v4 = vl4[m >> 2];
               const float u[4] = {u4.x, u4.y, u4.z, u4.w}, v[4] = {v4.x, v4.y, v4.z, v4.w};
+              // (past the chunk's end the last q is repeated: its weights
+              // are zero, and a larger q from the next chunk could push the
+              // chosen form past its range, to an infinite term times zero)
               double q[4];
 #pragma unroll
-              for (int k = 0; k < 4; ++k) q[k] = qk[m + k];
-              const double q_last = qk[min(m + 3, nqa - 1)];
+              for (int k = 0; k < 4; ++k) q[k] = qk[min(m + k, nqa - 1)];
+              const double q_last = q[3];
               auto acc4 = [&](auto&& eval) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -400,7 +402,6 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
   __shared__ __align__(16) float fj[kPaSub][QA];
   __shared__ double gjl[BJ * 3];
   __shared__ __align__(16) float iql[QA];
-  __shared__ double qvl[DIRECT ? QA : 1];
 
   const int lane = threadIdx.x;
   const int64_t t = blockIdx.x;
@@ -430,7 +431,6 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
   for (int m = lane; m < QA; m += kWave) {
     const double qm = m < nqa ? (DIRECT ? a.qdev[m0 + m] : a.q0 + (m0 + m) * dq) : 0.0;
     iql[m] = qm > 0.0 ? static_cast<float>(1.0 / qm) : 0.f;
-    if constexpr (DIRECT) qvl[m] = qm;
   }
 
   double gx = 0.0, gy = 0.0, gz = 0.0;
@@ -455,6 +455,15 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
       }
       __syncthreads();
       if constexpr (DIRECT) {
+        // per group of four q the product form, the one-FMA reduction or the
+        // exact one, chosen from the wave's extremes of 1/r as in k_adjoint;
+        // q through the scalar cache, groups past the chunk skipped, and the
+        // last q repeated inside the chunk's last group
+        using ConstDouble = const __attribute__((address_space(4))) double;
+        ConstDouble* qk = (ConstDouble*)(a.qdev + m0);
+        double kMagicV = kHalfMagic, kRoundV = kRoundMagic;
+        float kScale31 = 0x1p-31f;
+        asm volatile("" : "+v"(kMagicV), "+v"(kRoundV), "+v"(kScale31));
 #pragma unroll 1
         for (int jl = u0; jl < u0 + ns; ++jl) {
           asm volatile("" ::: "memory");
@@ -465,14 +474,36 @@ __global__ __launch_bounds__(kWave, 2) void k_adjoint_pa(AdjArgs a) {
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
           const double ir = rsqrt_f64(fmax(r2, 1e-60));
           const double rp = fmax(r2, 1e-60) * ir * kOneOverPi;
+          const bool ok = use && r2 > 0.0;
+          const float irf = static_cast<float>(ir);
+          const float ir_min = wave_extreme<false>(ok ? irf : __builtin_huge_valf());
+          const float ir_max = wave_extreme<true>(ok ? irf : 0.f);
+          constexpr double kPi = 0x1.921fb54442d18p+1;
+          const double q_small = 0.5 * kPi * ir_min, q_frac = 0.25 * kPi * ir_max, q_huge = 0x1p+19 * kPi * ir_min;
           float cc = 0.f, ss = 0.f;
           // (fully unrolled: a runtime index would put wi and wiq in scratch)
 #pragma unroll
-          for (int m = 0; m < QA; ++m) {
-            const SinCosF e = sincos_qr(qvl[m], rp);
-            const float u = wi[m] * f[m];
-            cc = fmaf(u, e.c, cc);
-            ss = fmaf(u * iql[m], e.s, ss);
+          for (int m = 0; m < QA; m += 4) {
+            if (m < nqa) {
+              double q[4];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) q[k] = qk[min(m + k, nqa - 1)];
+              auto acc4 = [&](auto&& eval) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  const SinCosF e = eval(q[k], rp);
+                  const float u = wi[m + k] * f[m + k];
+                  cc = fmaf(u, e.c, cc);
+                  ss = fmaf(u * iql[m + k], e.s, ss);
+                }
+              };
+              if (q[3] <= q_small)
+                acc4([&](double qq, double r) { return sincos_qr_small(qq, r); });
+              else if (q[0] >= q_frac && q[3] < q_huge)
+                acc4([&](double qq, double r) { return sincos_qr_frac(qq, r, kMagicV, kScale31); });
+              else
+                acc4([&](double qq, double r) { return sincos_qr_exact(qq, r, kRoundV); });
+            }
           }
           const double G = adj_force_direct(use && r2 > 0.0, ir, cc, ss);
           const double cx = G * dx, cy = G * dy, cz = G * dz;
