@@ -294,6 +294,31 @@ def _grad_check(sd, m, w, atoms=None, with_profile=False):
     return out
 
 
+@pytest.mark.parametrize("per_atom", [False, True])
+@pytest.mark.parametrize("grid", ["log_64", "two_chunks_sparse"])
+def test_direct_adjoint_form_transitions(sd, per_atom, grid):
+    """Pairs from 1 to 400 A apart on a log grid from 1e-3: within one pair
+    t = q r / pi crosses 1/4 and 1/2 at different groups of four q, so the
+    adjoint's groups take the product form, the one-FMA reduction (whose
+    cosine carries the sign of the sum's low word) and the exact one, and
+    switch between them.  The sparse grid has 525 q, two adjoint chunks, and
+    jumps by a factor up to 100 at the end, past the first chunk's range."""
+    say(f"direct adjoint forms, grid {grid}, per_atom={per_atom}")
+    if grid == "log_64":
+        q = W.log_grid(1e-3, 1.0, 64)
+    else:
+        q = np.concatenate([W.log_grid(1e-3, 0.05, 520), [5.0, 10.0, 20.0, 40.0, 80.0]])
+    rng = np.random.default_rng(805)
+    x = np.concatenate([[0.0, 1.0, 2.5], np.sort(rng.uniform(5.0, 400.0, 45))])
+    pts = np.stack([x, rng.normal(0.0, 1.0, x.size), rng.normal(0.0, 1.0, x.size)], axis=1).astype(np.float32)
+    types = rng.integers(0, 2, size=x.size).astype(np.int32)
+    m = W.Molecule("line", pts, types, W.gaussian_table([6.0, 8.0], [0.5, 0.9], q), q)
+    if per_atom:
+        m = W.with_per_atom_factors(m, 806)
+    w = rng.normal(size=len(q))
+    _grad_check(sd, m, w)
+
+
 @pytest.mark.parametrize("n", [2, 3, 65, 129, 300])
 def test_nonuniform_gradient_sizes(sd, n):
     say(f"gradient on a random grid, N={n}")
